@@ -1,0 +1,585 @@
+/*
+ * gpcg_ref.c -- plain FP64 CPU reference ("oracle") for GPCG.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header or constant table with the
+ * HIP implementation.
+ *
+ * What it computes (Benson, McInnes & More, "GPCG: a case study in the
+ * performance and scalability of optimization algorithms", arXiv cs/0101018):
+ *
+ *   minimise q(x) = 1/2 x'Ax - b'x  subject to  l <= x <= u,  A sparse SPD
+ *
+ * (the paper's Section 2 writes +b'x; this file uses g = Ax - b throughout).
+ * The method is Algorithm GPCG of Section 3: gradient-projection iterates
+ * with a projected backtracking search from the exact 1-D minimiser along the
+ * projected gradient, stopped by the active-set test (pgstop1) or the
+ * relative-decrease test (pgstop2); conjugate gradients on the reduced system
+ * of the free variables, stopped by the relative-decrease test (cgstop1); a
+ * projected search along the CG direction; and, when the binding set equals
+ * the active set (cgstop3), a further CG pass on the same face with a smaller
+ * eta2.  Like the paper's own implementation (Section 4, "technique 1"), the
+ * reduced matrix A_k = Z_k' A Z_k is extracted explicitly for each CG phase.
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *  - the stopping norm is the Euclidean norm of the projected gradient and
+ *    tau = max(tol_abs, tol_rel * ||P grad q(x0)||);
+ *  - mu, the sufficient-decrease constant, is an option (default 0.01);
+ *  - alpha_0 of the gradient-projection search is recomputed at every
+ *    iterate y_j along -P grad q(y_j);
+ *  - the ratio tests (pgstop2, cgstop1) take the max over an empty set as
+ *    -infinity, so they can only fire from the second iterate on;
+ *  - a failed backtracking (more than max_backtrack halvings) ends the
+ *    gradient-projection phase; max_gp caps its iterates;
+ *  - cgstop3 multiplies eta2 by eta2_reduce and restarts CG from w = 0 on the
+ *    face of the new iterate, skipping the gradient-projection phase; eta2 is
+ *    reset to its initial value whenever a gradient-projection phase runs;
+ *  - a fixed variable (l_i = u_i) is always active and binding and its
+ *    projected-gradient component is 0;
+ *  - the termination test is applied after each gradient-projection phase and
+ *    after each projected search;
+ *  - decreases of q are evaluated as g's + 1/2 s'As (equal to q(x+s)-q(x)) and
+ *    the CG decrease as 1/2 alpha_j rho'rho (equal to q_k(w_{j-1})-q_k(w_j)).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
+ * round-to-nearest, sequential sums in index order).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef ORA_MUTANT
+#define ORA_MUTANT 0 /* >0 plants a deliberate mistake (tests of the pins) */
+#endif
+
+enum {
+  ORA_OK = 0,
+  ORA_MAXIT = 1,
+  ORA_STAGNATED = 2,
+  ORA_ERR_ARG = -1,
+  ORA_ERR_BOUNDS = -2,
+  ORA_ERR_NAN = -3,
+  ORA_ERR_NOT_SPD = -4,
+};
+
+typedef struct {
+  int64_t n;
+  const int32_t *rowptr; /* n+1 */
+  const int32_t *colind; /* nnz */
+  const double *vals;    /* nnz */
+} ora_csr;
+
+typedef struct {
+  double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
+  int32_t max_outer, max_gp, max_backtrack, max_cg; /* max_cg <= 0: m_k */
+} ora_options;
+
+typedef struct {
+  int32_t status, outer_iters, gp_iters, cg_iters;
+  int32_t backtracks, face_repeats, cg_phases, x0_projected;
+  double pg0, pg, tau, q;
+  int64_t n_free, n_lower, n_upper;
+  double *trace_q;    /* optional: q after every projected search */
+  int64_t *trace_act; /* optional: |A(x)| before each CG phase and after
+                         the projected search that follows it (2 per entry) */
+  int32_t trace_cap, trace_len;
+} ora_stats;
+
+void ora_default_options(ora_options *o) {
+  o->tol_rel = 1e-8;
+  o->tol_abs = 0.0;
+  o->eta1 = 0.1;   /* Section 5: eta_1 = 0.1 */
+  o->eta2 = 0.05;  /* Section 5: eta_2 = 0.05 */
+  o->eta2_reduce = 0.1;
+  o->mu = 0.01;
+  o->max_outer = 100000;
+  o->max_gp = 50;
+  o->max_backtrack = 60;
+  o->max_cg = 0;
+}
+
+/* ----------------------------------------------------------- building blocks */
+
+/* y = A x (CSR, row by row, entries in stored order). */
+void ora_matvec(const ora_csr *A, const double *x, double *y) {
+  for (int64_t i = 0; i < A->n; ++i) {
+    double s = 0.0;
+    for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+      s += A->vals[k] * x[A->colind[k]];
+    y[i] = s;
+  }
+}
+
+double ora_dot(int64_t n, const double *a, const double *b) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+/* Gradient of q: g = A x - b. */
+void ora_gradient(const ora_csr *A, const double *x, const double *b, double *g) {
+  ora_matvec(A, x, g);
+  for (int64_t i = 0; i < A->n; ++i) {
+#if ORA_MUTANT == 7
+    g[i] = b[i] - g[i];
+#else
+    g[i] = g[i] - b[i];
+#endif
+  }
+}
+
+/* q(x) = 1/2 x'Ax - b'x (Section 2, with the sign of b as above). */
+double ora_objective(const ora_csr *A, const double *b, const double *x) {
+  double *Ax = (double *)malloc(sizeof(double) * (size_t)(A->n > 0 ? A->n : 1));
+  ora_matvec(A, x, Ax);
+  double q = 0.5 * ora_dot(A->n, x, Ax) - ora_dot(A->n, b, x);
+  free(Ax);
+  return q;
+}
+
+/* Projection onto the box: the median of {l_i, u_i, v_i} (Section 3). */
+static double mid3(double l, double u, double v) {
+  if (v < l) return l;
+#if ORA_MUTANT == 8
+  if (v > u) return l;
+#else
+  if (v > u) return u;
+#endif
+  return v;
+}
+
+void ora_project(int64_t n, const double *l, const double *u, const double *v, double *out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = mid3(l[i], u[i], v[i]);
+}
+
+/* Active set A(x): x_i at one of its bounds (Section 2). */
+static int is_active(double x, double l, double u) { return x == l || x == u; }
+
+/* Binding set B(x): at l with d_i q >= 0, or at u with d_i q <= 0 (Section 2). */
+static int is_binding(double x, double l, double u, double g) {
+#if ORA_MUTANT == 9
+  return (x == l && g <= 0.0) || (x == u && g >= 0.0);
+#else
+  return (x == l && g >= 0.0) || (x == u && g <= 0.0);
+#endif
+}
+
+/* Projected gradient, eq. (proj-gradient) of Section 2; a fixed variable
+ * (l_i = u_i) gets 0. */
+static double proj_grad_1(double x, double l, double u, double g) {
+  if (x == l && x == u) return 0.0;
+  if (x == l) return g < 0.0 ? g : 0.0;
+#if ORA_MUTANT == 1
+  if (x == u) return g < 0.0 ? g : 0.0;
+#else
+  if (x == u) return g > 0.0 ? g : 0.0;
+#endif
+  return g;
+}
+
+void ora_proj_gradient(int64_t n, const double *x, const double *l, const double *u,
+                       const double *g, double *pg) {
+  for (int64_t i = 0; i < n; ++i) pg[i] = proj_grad_1(x[i], l[i], u[i], g[i]);
+}
+
+double ora_proj_gradient_norm(int64_t n, const double *x, const double *l, const double *u,
+                              const double *g) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double p = proj_grad_1(x[i], l[i], u[i], g[i]);
+    s += p * p;
+  }
+  return sqrt(s);
+}
+
+/* Counts of the face of x: lower-active (x = l, including fixed), upper-active
+ * (x = u != l), and active-but-not-binding variables.  The last is zero exactly
+ * when B(x) = A(x). */
+void ora_classify(int64_t n, const double *x, const double *l, const double *u,
+                  const double *g, int64_t *n_lower, int64_t *n_upper,
+                  int64_t *n_nonbinding) {
+  int64_t lo = 0, up = 0, nb = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (x[i] == l[i]) ++lo;
+    else if (x[i] == u[i]) ++up;
+    if (is_active(x[i], l[i], u[i]) && !is_binding(x[i], l[i], u[i], g[i])) ++nb;
+  }
+  *n_lower = lo;
+  *n_upper = up;
+  *n_nonbinding = nb;
+}
+
+/* Initial step of the gradient-projection search, eq. (bqpls): along
+ * d = -P grad q(y) the model is a 1-D quadratic in alpha whose minimiser is
+ * ||d||^2 / d'Ad (g'P grad q = ||P grad q||^2).  Returns d'd and d'Ad. */
+void ora_gp_alpha0(const ora_csr *A, const double *y, const double *l, const double *u,
+                   const double *g, double *dd, double *dAd) {
+  int64_t n = A->n;
+  double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *Ad = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  ora_proj_gradient(n, y, l, u, g, d);
+  ora_matvec(A, d, Ad);
+  *dd = ora_dot(n, d, d);
+  *dAd = ora_dot(n, d, Ad);
+  free(d);
+  free(Ad);
+}
+
+/* One trial point of a projected search: ynew = P[y + alpha dir], s = ynew - y,
+ * the decrease pieces g's and s'As (q(ynew) - q(y) = g's + 1/2 s'As), and the
+ * number of variables whose membership in the active set changes. */
+void ora_trial(const ora_csr *A, const double *y, const double *dir, double alpha,
+               const double *l, const double *u, const double *g, double *ynew,
+               double *gs, double *sAs, int64_t *nchg) {
+  int64_t n = A->n;
+  double *s = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *As = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  int64_t c = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t = y[i] + alpha * dir[i];
+    ynew[i] = mid3(l[i], u[i], t);
+    s[i] = ynew[i] - y[i];
+    if (is_active(ynew[i], l[i], u[i]) != is_active(y[i], l[i], u[i])) ++c;
+  }
+  ora_matvec(A, s, As);
+  *gs = ora_dot(n, g, s);
+  *sAs = ora_dot(n, s, As);
+  *nchg = c;
+  free(s);
+  free(As);
+}
+
+/* q(y + s) - q(y) = g's + 1/2 s'As, exactly, for the quadratic q. */
+double ora_decrease(double gs, double sAs) {
+#if ORA_MUTANT == 2
+  return gs + sAs;
+#else
+  return gs + 0.5 * sAs;
+#endif
+}
+
+/* Reduced matrix A_k = Z_k' A Z_k for the index set F (the free variables,
+ * listed in increasing order): rows and columns of A whose index is in F. */
+static void extract_submatrix(const ora_csr *A, const int64_t *F, int64_t m, const int64_t *pos,
+                              int32_t **rp, int32_t **ci, double **va) {
+  int64_t nnz = 0;
+  for (int64_t a = 0; a < m; ++a) {
+    int64_t i = F[a];
+    for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+      if (pos[A->colind[k]] >= 0) ++nnz;
+  }
+  *rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
+  *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  *va = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  int64_t t = 0;
+  (*rp)[0] = 0;
+  for (int64_t a = 0; a < m; ++a) {
+    int64_t i = F[a];
+    for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+      int64_t p = pos[A->colind[k]];
+      if (p >= 0) {
+        (*ci)[t] = (int32_t)p;
+        (*va)[t] = A->vals[k];
+        ++t;
+      }
+    }
+    (*rp)[a + 1] = (int32_t)t;
+  }
+}
+
+/* Conjugate gradients on the reduced problem min 1/2 w'A_k w + r_k'w from
+ * w_0 = 0 (Section 3, eq. (cg2)), stopped by the relative-decrease test
+ * (cgstop1) with tolerance eta, when the residual vanishes, or after max_cg
+ * iterations.  `free_mask[i]` != 0 marks the free variables; the result is
+ * d = Z_k w written into d (zero on the active set).  Returns ORA_OK or
+ * ORA_ERR_NOT_SPD; *iters gets the number of CG iterations; decs (optional,
+ * capacity dec_cap) receives q_k(w_{j-1}) - q_k(w_j) for each iteration. */
+int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const double *g,
+                   double eta, int32_t max_cg, double *d, int32_t *iters, double *decs,
+                   int32_t dec_cap) {
+  int64_t n = A->n;
+  int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (free_mask[i]) {
+      pos[i] = m;
+      F[m++] = i;
+    } else {
+      pos[i] = -1;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) d[i] = 0.0;
+  *iters = 0;
+  if (m == 0) {
+    free(pos);
+    free(F);
+    return ORA_OK;
+  }
+  int32_t *rp, *ci;
+  double *va;
+  extract_submatrix(A, F, m, pos, &rp, &ci, &va);
+  ora_csr Ak = {m, rp, ci, va};
+
+  double *w = (double *)calloc((size_t)m, sizeof(double));
+  double *rho = (double *)malloc(sizeof(double) * (size_t)m);
+  double *p = (double *)malloc(sizeof(double) * (size_t)m);
+  double *q = (double *)malloc(sizeof(double) * (size_t)m);
+  /* r_k = Z_k' grad q(x_k); the residual of A_k w + r_k = 0 at w = 0 is -r_k */
+  for (int64_t a = 0; a < m; ++a) {
+#if ORA_MUTANT == 6
+    rho[a] = g[F[a]];
+#else
+    rho[a] = -g[F[a]];
+#endif
+    p[a] = rho[a];
+  }
+  double rr = ora_dot(m, rho, rho);
+  int64_t cap = max_cg > 0 ? max_cg : m;
+  double decmax = -INFINITY;
+  int status = ORA_OK;
+  int32_t j = 0;
+  if (rr > 0.0) {
+    for (;;) {
+      ora_matvec(&Ak, p, q);
+      double pq = ora_dot(m, p, q);
+      if (!(pq > 0.0)) {
+        status = ORA_ERR_NOT_SPD;
+        break;
+      }
+      double alpha = rr / pq;
+      for (int64_t a = 0; a < m; ++a) w[a] += alpha * p[a];
+      for (int64_t a = 0; a < m; ++a) rho[a] -= alpha * q[a];
+      double rr_new = ora_dot(m, rho, rho);
+      ++j;
+#if ORA_MUTANT == 10
+      double dec = alpha * rr;
+#else
+      double dec = 0.5 * alpha * rr; /* q_k(w_{j-1}) - q_k(w_j) */
+#endif
+      if (decs && j <= dec_cap) decs[j - 1] = dec;
+      int stop = (rr_new == 0.0) || (j >= 2 && dec <= eta * decmax) || (j >= cap);
+      if (dec > decmax) decmax = dec;
+      if (stop) break;
+#if ORA_MUTANT == 5
+      double beta = rr / rr_new;
+#else
+      double beta = rr_new / rr;
+#endif
+      for (int64_t a = 0; a < m; ++a) p[a] = rho[a] + beta * p[a];
+      rr = rr_new;
+    }
+  }
+  for (int64_t a = 0; a < m; ++a) d[F[a]] = w[a];
+  *iters = j;
+  free(w);
+  free(rho);
+  free(p);
+  free(q);
+  free(rp);
+  free(ci);
+  free(va);
+  free(pos);
+  free(F);
+  return status;
+}
+
+/* ----------------------------------------------------------- Algorithm GPCG */
+
+static int has_nan(int64_t n, const double *v) {
+  for (int64_t i = 0; i < n; ++i)
+    if (v[i] != v[i]) return 1;
+  return 0;
+}
+
+static int finish(ora_stats *st, int status, const ora_csr *A, const double *b,
+                  const double *l, const double *u, const double *x, const double *g) {
+  int64_t lo, up, nb;
+  st->status = status;
+  st->pg = ora_proj_gradient_norm(A->n, x, l, u, g);
+  ora_classify(A->n, x, l, u, g, &lo, &up, &nb);
+  st->n_lower = lo;
+  st->n_upper = up;
+  st->n_free = A->n - lo - up;
+  st->q = ora_objective(A, b, x);
+  return status;
+}
+
+/* Solve the QP from x0; x receives the answer, g (nullable) its gradient. */
+int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u,
+             const double *x0, const ora_options *opt_in, double *x, double *g_out,
+             ora_stats *st) {
+  ora_options opt;
+  if (opt_in) opt = *opt_in;
+  else ora_default_options(&opt);
+  int64_t n = A->n;
+  double *trace_q = st->trace_q;
+  int64_t *trace_act = st->trace_act;
+  int32_t trace_cap = st->trace_cap;
+  memset(st, 0, sizeof(*st));
+  st->trace_q = trace_q;
+  st->trace_act = trace_act;
+  st->trace_cap = trace_cap;
+  if (n <= 0) return st->status = ORA_ERR_ARG;
+  if (has_nan(n, b) || has_nan(n, l) || has_nan(n, u) || has_nan(n, x0))
+    return st->status = ORA_ERR_NAN;
+  for (int64_t i = 0; i < n; ++i)
+    if (l[i] > u[i]) return st->status = ORA_ERR_BOUNDS;
+
+  size_t bytes = sizeof(double) * (size_t)n;
+  double *g = (double *)malloc(bytes);
+  double *y = (double *)malloc(bytes);
+  double *dir = (double *)malloc(bytes);
+  double *d = (double *)malloc(bytes);
+  unsigned char *fm = (unsigned char *)malloc((size_t)n);
+  int status = ORA_OK;
+
+  /* x_0 must lie in the feasible set; an outside start is projected. */
+  ora_project(n, l, u, x0, x);
+  for (int64_t i = 0; i < n; ++i)
+    if (x[i] != x0[i]) {
+      st->x0_projected = 1;
+      break;
+    }
+  ora_gradient(A, x, b, g);
+  double pgn = ora_proj_gradient_norm(n, x, l, u, g);
+  st->pg0 = pgn;
+  double tau = opt.tol_abs;
+  if (opt.tol_rel * pgn > tau) tau = opt.tol_rel * pgn;
+  st->tau = tau;
+  if (pgn <= tau) goto done;
+
+  for (;;) {
+    /* ---- gradient-projection phase, eqs. (next-y)-(pgstop2) ---- */
+    int32_t gp_accepts = 0;
+    {
+      double decmax = -INFINITY;
+      for (int32_t j = 1;; ++j) {
+        double dd, dAd;
+        ora_gp_alpha0(A, x, l, u, g, &dd, &dAd);
+        if (dd == 0.0) goto done; /* P grad q = 0: x is optimal */
+        if (!(dAd > 0.0)) {
+          status = ORA_ERR_NOT_SPD;
+          goto done;
+        }
+#if ORA_MUTANT == 4
+        double alpha = dAd / dd;
+#else
+        double alpha = dd / dAd;
+#endif
+        for (int64_t i = 0; i < n; ++i) dir[i] = -g[i];
+        int accepted = 0;
+        double gs = 0, sAs = 0, delta = 0;
+        int64_t nchg = 0;
+        for (int32_t bt = 0; bt <= opt.max_backtrack; ++bt) {
+          ora_trial(A, x, dir, alpha, l, u, g, y, &gs, &sAs, &nchg);
+          delta = ora_decrease(gs, sAs);
+          if (delta <= opt.mu * gs) {
+            accepted = 1;
+            break;
+          }
+          alpha *= 0.5;
+          ++st->backtracks;
+        }
+        if (!accepted) break; /* no sufficient decrease above rounding level */
+        memcpy(x, y, bytes);
+        ora_gradient(A, x, b, g);
+        ++st->gp_iters;
+        ++gp_accepts;
+        double dec = -delta;
+        int stop = (nchg == 0) || (j >= 2 && dec <= opt.eta1 * decmax) || (j >= opt.max_gp);
+        if (dec > decmax) decmax = dec;
+        if (stop) break;
+      }
+      pgn = ora_proj_gradient_norm(n, x, l, u, g);
+      if (pgn <= tau) goto done;
+    }
+
+    /* ---- CG on the face, then projected search; repeat while B = A ---- */
+    double eta = opt.eta2;
+    for (;;) {
+      int64_t m = 0;
+      for (int64_t i = 0; i < n; ++i) {
+#if ORA_MUTANT == 3
+        fm[i] = !is_binding(x[i], l[i], u[i], g[i]);
+#else
+        fm[i] = !is_active(x[i], l[i], u[i]);
+#endif
+        m += fm[i];
+      }
+      int64_t act_before = n - m;
+      if (m == 0) {
+        /* no free variable: back to gradient projection, unless that phase
+         * could not move at all (nothing left above rounding level) */
+        if (gp_accepts == 0) {
+          status = ORA_STAGNATED;
+          goto done;
+        }
+        break;
+      }
+      int32_t it = 0;
+      int cgs = ora_reduced_cg(A, fm, g, eta, opt.max_cg, d, &it, NULL, 0);
+      st->cg_iters += it;
+      ++st->cg_phases;
+      if (cgs != ORA_OK) {
+        status = cgs;
+        goto done;
+      }
+      /* projected search along d_k, eq. (cglsstop2), alpha = 1, 1/2, ... */
+      double alpha = 1.0;
+      int accepted = 0;
+      double gs = 0, sAs = 0, delta = 0;
+      int64_t nchg = 0;
+      for (int32_t bt = 0; bt <= opt.max_backtrack; ++bt) {
+        ora_trial(A, x, d, alpha, l, u, g, y, &gs, &sAs, &nchg);
+        delta = ora_decrease(gs, sAs);
+        if (delta <= opt.mu * gs) {
+          accepted = 1;
+          break;
+        }
+        alpha *= 0.5;
+        ++st->backtracks;
+      }
+      if (accepted) memcpy(x, y, bytes);
+      ora_gradient(A, x, b, g);
+      ++st->outer_iters;
+      if (st->trace_len < st->trace_cap) {
+        if (st->trace_q) st->trace_q[st->trace_len] = ora_objective(A, b, x);
+        if (st->trace_act) {
+          int64_t act_after = 0;
+          for (int64_t i = 0; i < n; ++i) act_after += is_active(x[i], l[i], u[i]);
+          st->trace_act[2 * st->trace_len] = act_before;
+          st->trace_act[2 * st->trace_len + 1] = act_after;
+        }
+        ++st->trace_len;
+      }
+      pgn = ora_proj_gradient_norm(n, x, l, u, g);
+      if (pgn <= tau) goto done;
+      if (!accepted) {
+        status = ORA_STAGNATED;
+        goto done;
+      }
+      if (st->outer_iters >= opt.max_outer) {
+        status = ORA_MAXIT;
+        goto done;
+      }
+      int64_t lo, up, nb;
+      ora_classify(n, x, l, u, g, &lo, &up, &nb);
+      if (nb != 0) break; /* B(x) != A(x): next GPCG iteration starts with GP */
+      eta *= opt.eta2_reduce; /* cgstop3: same face, more accurate CG */
+      ++st->face_repeats;
+    }
+  }
+
+done:
+  finish(st, status, A, b, l, u, x, g);
+  if (g_out) memcpy(g_out, g, bytes);
+  free(g);
+  free(y);
+  free(dir);
+  free(d);
+  free(fm);
+  return st->status;
+}

@@ -1,0 +1,298 @@
+"""Pins of the GPCG oracle against facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` function takes an ``oracle.Oracle`` and raises AssertionError
+when the oracle disagrees with something that does not depend on the oracle:
+closed forms, brute-force enumeration, an independent exact solver, textbook
+CG written here from its definition, exact rational arithmetic, hand-derived
+cases of the paper's definitions.  ``test_oracle_pins.py`` runs them against
+the oracle; ``test_oracle_mutants.py`` runs them against builds of the oracle
+with planted mistakes and requires every mistake to be caught.
+"""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+import scipy.fft
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import instances
+from oracle import exact
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+TIGHT = dict(tol_rel=1e-13, max_outer=500)
+
+
+def _load_cases():
+    rows = []
+    with open(os.path.join(GOLDEN, "proj_gradient_cases.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append([float(v) for v in line.split()])
+    return np.array(rows)
+
+
+def _q(A, b, x):
+    return 0.5 * x @ (A @ x) - b @ x
+
+
+# ---------------------------------------------------------------- definitions
+
+def pin_projection_is_median(o):
+    """P[v] = mid(l, u, v), the componentwise median (Section 3)."""
+    rng = np.random.default_rng(11)
+    n = 4000
+    a, c = rng.standard_normal(n), rng.standard_normal(n)
+    l, u = np.minimum(a, c), np.maximum(a, c)
+    l[:300] = -np.inf
+    u[300:600] = np.inf
+    u[600:700] = l[600:700]
+    v = 2.0 * rng.standard_normal(n)
+    v[700:800] = l[700:800]
+    got = o.project(l, u, v)
+    want = np.median(np.stack([l, u, v]), axis=0)
+    assert np.array_equal(got, want)
+
+
+def pin_projected_gradient_cases(o):
+    """Hand cases of eq. (proj-gradient) and the binding set (Section 2)."""
+    T = _load_cases()
+    x, l, u, g, pg, act, bind = T.T
+    got = o.proj_gradient(x, l, u, g)
+    assert np.array_equal(got, pg), (got, pg)
+    for k in range(len(x)):
+        lo, up, nb = o.classify(x[k:k + 1], l[k:k + 1], u[k:k + 1], g[k:k + 1])
+        assert lo + up == int(act[k]), k
+        assert nb == int(act[k] and not bind[k]), k
+    assert np.isclose(o.proj_gradient_norm(x, l, u, g), np.sqrt(np.sum(pg * pg)), rtol=1e-15)
+
+
+def pin_gradient_matches_sparse_library(o):
+    """g = A x - b against SciPy's CSR product."""
+    inst = instances.config1(seed=3)
+    csr = inst.csr()
+    A = exact.csr_matrix(csr)
+    x = np.random.default_rng(2).standard_normal(inst.n)
+    g = o.gradient(csr, x, inst.b)
+    ref = A @ x - inst.b
+    assert np.allclose(g, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+# ------------------------------------------------------------- single steps
+
+def pin_alpha0_minimises_along_projected_gradient(o):
+    """alpha_0 of eq. (bqpls) is the minimiser of q(y - alpha P grad q(y))."""
+    inst = instances.config0(seed=5)
+    csr = inst.csr()
+    A = exact.csr_matrix(csr)
+    y = inst.x0
+    g = A @ y - inst.b
+    dd, dAd = o.gp_alpha0(csr, y, inst.l, inst.u, g)
+    a0 = dd / dAd
+    d = o.proj_gradient(y, inst.l, inst.u, g)
+    f = lambda a: _q(A, inst.b, y - a * d)
+    assert a0 > 0
+    for fac in (0.999, 1.001, 0.9, 1.1):
+        assert f(a0) < f(fac * a0)
+
+
+def pin_decrease_identity_exact(o):
+    """q(y') - q(y) = g's + 1/2 s'As, checked in exact rational arithmetic."""
+    inst = instances.tiny_dense(6, seed=21)
+    A = inst.dense
+    csr = inst.csr()
+    y = np.clip(np.zeros(6), inst.l, inst.u)
+    g = A @ y - inst.b
+    ynew, gs, sAs, nchg = o.trial(csr, y, -g, 0.37, inst.l, inst.u, g)
+    delta = o.decrease(gs, sAs)
+    F = lambda v: [Fraction(float(t)) for t in v]
+    Af = [[Fraction(float(t)) for t in row] for row in A]
+    bf = F(inst.b)
+
+    def qf(v):
+        vf = F(v)
+        Av = [sum(Af[i][j] * vf[j] for j in range(6)) for i in range(6)]
+        return Fraction(1, 2) * sum(vf[i] * Av[i] for i in range(6)) - sum(bf[i] * vf[i] for i in range(6))
+
+    exact_delta = float(qf(ynew) - qf(y))
+    assert abs(delta - exact_delta) <= 1e-12 * (abs(exact_delta) + abs(gs))
+    # the trial point is the projection of y - alpha g
+    assert np.array_equal(ynew, np.median(np.stack([inst.l, inst.u, y - 0.37 * g]), axis=0))
+    act_old = (y == inst.l) | (y == inst.u)
+    act_new = (ynew == inst.l) | (ynew == inst.u)
+    assert nchg == int(np.sum(act_old != act_new))
+
+
+def _textbook_cg(A, rhs, iters):
+    """Hestenes-Stiefel CG for A w = rhs from w = 0, written from the textbook."""
+    w = np.zeros_like(rhs)
+    r = rhs.copy()
+    p = r.copy()
+    out = []
+    for _ in range(iters):
+        Ap = A @ p
+        a = (r @ r) / (p @ Ap)
+        w = w + a * p
+        r_new = r - a * Ap
+        out.append(w.copy())
+        if r_new @ r_new == 0:
+            break
+        p = r_new + (r_new @ r_new) / (r @ r) * p
+        r = r_new
+    return out
+
+
+def pin_reduced_cg_is_textbook_cg(o):
+    """Unconstrained face, eta -> 0: the iterates are textbook CG on A w = -g,
+    the CG decreases equal q_k(w_{j-1}) - q_k(w_j), and m steps solve it."""
+    inst = instances.tiny_dense(8, seed=4)
+    A = inst.dense
+    csr = inst.csr()
+    g = np.random.default_rng(9).standard_normal(8)
+    mask = np.ones(8, np.uint8)
+    st, d, it, decs = o.reduced_cg(csr, mask, g, 1e-300)
+    assert st == 0 and 1 <= it <= 8
+    ref = _textbook_cg(A, -g, 8)
+    assert np.allclose(d, ref[it - 1], rtol=1e-9, atol=1e-12)
+    assert np.allclose(d, np.linalg.solve(A, -g), rtol=1e-8, atol=1e-10)
+    qk = lambda w: 0.5 * w @ A @ w + g @ w
+    prev = 0.0
+    for j in range(it):
+        cur = qk(ref[j])
+        assert np.isclose(decs[j], prev - cur, rtol=1e-8), (j, decs[j], prev - cur)
+        prev = cur
+    # a few iterations with max_cg: again the textbook iterates
+    st, d3, it3, _ = o.reduced_cg(csr, mask, g, 1e-300, max_cg=3)
+    assert it3 == 3 and np.allclose(d3, ref[2], rtol=1e-10, atol=1e-13)
+
+
+def pin_reduced_cg_stays_on_face(o):
+    """With variables held fixed (mask 0) the direction is zero there and the
+    free part solves A_FF d_F = -g_F (eq. (cg2))."""
+    inst = instances.tiny_dense(8, seed=8)
+    A = inst.dense
+    g = np.random.default_rng(1).standard_normal(8)
+    mask = np.array([1, 0, 1, 1, 0, 1, 0, 1], np.uint8)
+    st, d, it, _ = o.reduced_cg(inst.csr(), mask, g, 1e-300)
+    F = mask.astype(bool)
+    assert st == 0 and np.all(d[~F] == 0.0) and it <= F.sum()
+    assert np.allclose(d[F], np.linalg.solve(A[np.ix_(F, F)], -g[F]), rtol=1e-9, atol=1e-12)
+
+
+# ---------------------------------------------------------------- whole method
+
+def pin_brute_force_tiny(o, count=40):
+    """Tiny QPs (n <= 8, mixed bound kinds incl. +-inf and l = u): GPCG's x
+    equals the solution found by enumerating all 3^n faces."""
+    for seed in range(count):
+        n = 1 + seed % 8
+        inst = instances.tiny_dense(n, seed=100 + seed)
+        ref = exact.brute_force(inst.dense, inst.b, inst.l, inst.u)
+        assert ref is not None
+        x, _, st = o.solve_instance(inst, **TIGHT)
+        assert st["status"] == 0, (seed, st)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(x - ref).max() <= 1e-9 * scale, (seed, x, ref)
+        assert np.all(x >= inst.l) and np.all(x <= inst.u)
+
+
+def pin_diagonal_closed_form(o):
+    """Diagonal A: x*_i = mid(l_i, u_i, b_i / a_ii)."""
+    inst = instances.diagonal(200, seed=3)
+    x, _, st = o.solve_instance(inst, **TIGHT)
+    d = np.diag(inst.dense)
+    want = np.minimum(np.maximum(inst.b / d, inst.l), inst.u)
+    assert st["status"] == 0
+    assert np.allclose(x, want, rtol=1e-12, atol=1e-13)
+
+
+def pin_unconstrained_laplacian_dst(o):
+    """l = -inf, u = +inf on the 5-point Laplacian: x* = A^{-1} b, computed by
+    the discrete sine transform that diagonalises A (closed-form eigenvalues
+    4/h^2 (sin^2(p pi h/2) + sin^2(q pi h/2)))."""
+    N = 31
+    inst = instances.unconstrained(N, instances.OP_CONST, seed=2)
+    h = 1.0 / (N + 1)
+    k = np.arange(1, N + 1)
+    lam1 = np.sin(k * np.pi * h / 2) ** 2
+    Lam = 4.0 / h**2 * (lam1[:, None] + lam1[None, :])
+    B = inst.b.reshape(N, N)
+    X = scipy.fft.idstn(scipy.fft.dstn(B, type=1) / Lam, type=1)
+    x, _, st = o.solve_instance(inst, **TIGHT)
+    assert st["status"] == 0
+    assert st["gp_iters"] == 1  # A(x) stays empty: pgstop1 ends GP at j = 1
+    # with no active bound the exact 1-D minimiser (GP) and the unit CG step
+    # (projected search) both satisfy sufficient decrease: no backtracking
+    assert st["backtracks"] == 0
+    assert np.abs(x - X.ravel()).max() <= 1e-9 * np.abs(X).max()
+
+
+def pin_unconstrained_varcoef_direct(o):
+    """Unconstrained variable-coefficient operator against a sparse direct solve."""
+    inst = instances.unconstrained(40, instances.OP_VAR, seed=6)
+    A = exact.csr_matrix(inst.csr())
+    want = spla.spsolve(A.tocsc(), inst.b)
+    x, _, st = o.solve_instance(inst, **TIGHT)
+    assert st["status"] == 0
+    assert np.abs(x - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def pin_manufactured(o):
+    """Problems built around a known x* and known lower/upper/free sets."""
+    for op in (instances.OP_CONST, instances.OP_VAR):
+        inst = instances.manufactured(24, op, seed=7)
+        xs, status = inst.meta["x_star"], inst.meta["status"]
+        x, g, st = o.solve_instance(inst, **TIGHT)
+        assert st["status"] == 0, st
+        assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max(), op
+        assert np.array_equal(x == inst.l, status == 1), op
+        assert np.array_equal(x == inst.u, status == 2), op
+        assert st["n_upper"] == int(np.sum(status == 2))
+
+
+def pin_matches_independent_exact_solver(o):
+    """The obstacle problem (n = 2500) against primal-dual active set + sparse
+    direct solves, a method sharing nothing with GPCG."""
+    inst = instances.config0(seed=1)
+    csr = inst.csr()
+    x, g, st = o.solve_instance(inst, **TIGHT)
+    xs, info = exact.polish(csr, inst.b, inst.l, inst.u, None)
+    assert info["converged"] and st["status"] == 0
+    assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
+    assert np.array_equal(x == inst.l, xs == inst.l)
+
+
+def pin_invariants(o):
+    """q decreases at every projected search (sufficient decrease), the active
+    set does not shrink across a CG step + projected search (the CG direction
+    is zero on A(x_k)), and the answer is feasible."""
+    inst = instances.config0(seed=2)
+    x, g, st = o.solve_instance(inst, trace_cap=1000)
+    tq = st["trace_q"]
+    assert len(tq) == st["outer_iters"] >= 2
+    assert np.all(np.diff(tq) < 0)
+    act = st["trace_act"]
+    assert np.all(act[:, 1] >= act[:, 0])
+    assert np.all(x >= inst.l) and np.all(x <= inst.u)
+
+
+ALL_PINS = [
+    pin_projection_is_median,
+    pin_projected_gradient_cases,
+    pin_gradient_matches_sparse_library,
+    pin_alpha0_minimises_along_projected_gradient,
+    pin_decrease_identity_exact,
+    pin_reduced_cg_is_textbook_cg,
+    pin_reduced_cg_stays_on_face,
+    pin_brute_force_tiny,
+    pin_diagonal_closed_form,
+    pin_unconstrained_laplacian_dst,
+    pin_unconstrained_varcoef_direct,
+    pin_manufactured,
+    pin_matches_independent_exact_solver,
+    pin_invariants,
+]
