@@ -44,7 +44,7 @@ class Options(C.Structure):
     _fields_ = [("tol_rel", C.c_double), ("tol_abs", C.c_double), ("eta1", C.c_double),
                 ("eta2", C.c_double), ("eta2_reduce", C.c_double), ("mu", C.c_double),
                 ("max_outer", C.c_int32), ("max_gp", C.c_int32),
-                ("max_backtrack", C.c_int32), ("max_cg", C.c_int32)]
+                ("max_backtrack", C.c_int32), ("max_cg", C.c_int32), ("max_stall", C.c_int32)]
 
 
 class Stats(C.Structure):

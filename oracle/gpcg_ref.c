@@ -39,6 +39,9 @@
  *    projected-gradient component is 0;
  *  - the termination test is applied after each gradient-projection phase and
  *    after each projected search;
+ *  - below the rounding floor of FP64 the tests above can no longer fire, so
+ *    the solve stops as stagnated when ||P grad q|| after a projected search
+ *    has not improved on its best value for max_stall consecutive searches;
  *  - decreases of q are evaluated as g's + 1/2 s'As (equal to q(x+s)-q(x)) and
  *    the CG decrease as 1/2 alpha_j rho'rho (equal to q_k(w_{j-1})-q_k(w_j)).
  *
@@ -74,6 +77,7 @@ typedef struct {
 typedef struct {
   double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
   int32_t max_outer, max_gp, max_backtrack, max_cg; /* max_cg <= 0: m_k */
+  int32_t max_stall; /* outer iterations without a new best ||P grad q|| */
 } ora_options;
 
 typedef struct {
@@ -98,6 +102,7 @@ void ora_default_options(ora_options *o) {
   o->max_gp = 50;
   o->max_backtrack = 60;
   o->max_cg = 0;
+  o->max_stall = 25;
 }
 
 /* ----------------------------------------------------------- building blocks */
@@ -450,6 +455,8 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
   if (opt.tol_rel * pgn > tau) tau = opt.tol_rel * pgn;
   st->tau = tau;
   if (pgn <= tau) goto done;
+  double best_pg = pgn;
+  int32_t stall = 0;
 
   for (;;) {
     /* ---- gradient-projection phase, eqs. (next-y)-(pgstop2) ---- */
@@ -557,6 +564,13 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
       }
       pgn = ora_proj_gradient_norm(n, x, l, u, g);
       if (pgn <= tau) goto done;
+      if (pgn < best_pg) {
+        best_pg = pgn;
+        stall = 0;
+      } else if (++stall >= opt.max_stall) {
+        status = ORA_STAGNATED;
+        goto done;
+      }
       if (!accepted) {
         status = ORA_STAGNATED;
         goto done;

@@ -1,0 +1,64 @@
+"""The C ABI library loads and exports every function include/gpcg.h declares
+(CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpcg.h")
+LIB = os.path.join(ROOT, "paper_cs_0101018_amd", "libgpcg.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpcg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("gpcg_create", "gpcg_solve", "gpcg_destroy", "gpcg_workspace_bytes",
+                 "gpcg_batch_solve", "gpcg_server_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libgpcg.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    import paper_cs_0101018_amd as gpcg
+    assert sorted(gpcg.EXPORTED) == declared_functions()
+
+
+def test_host_side_validation_without_gpu():
+    """Descriptor and option checks run on the host before any device call."""
+    import paper_cs_0101018_amd as gpcg
+    op = gpcg.gpcg_operator(kind=gpcg.GPCG_OP_STENCIL5_CONST, nx=10, ny=10, w=-1.0)
+    nbytes = ctypes.c_size_t()
+    rc = gpcg.gpcg_workspace_bytes(ctypes.byref(op), None, ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_ERR_ARG
+    op.w = 121.0
+    rc = gpcg.gpcg_workspace_bytes(ctypes.byref(op), None, ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_OK and nbytes.value > 100 * 8 * 6
+    opt = gpcg.default_options(mu=0.7)
+    rc = gpcg.gpcg_workspace_bytes(ctypes.byref(op), ctypes.byref(opt), ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_ERR_ARG
+    opt = gpcg.default_options(tile=300)
+    rc = gpcg.gpcg_workspace_bytes(ctypes.byref(op), ctypes.byref(opt), ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_ERR_ARG
+    # a workspace that is too small is refused before any device work
+    h = ctypes.c_void_p()
+    rc = gpcg.gpcg_create(ctypes.byref(op), None, ctypes.c_void_p(256), 16, None, ctypes.byref(h))
+    assert rc == gpcg.GPCG_ERR_WORKSPACE
+    # the server refuses CSR operators and over-sized requests up front
+    csr = gpcg.gpcg_operator(kind=gpcg.GPCG_OP_CSR, n=4, nnz=4, rowptr=8, colind=8, vals=8)
+    rc = gpcg.gpcg_server_footprint(ctypes.byref(csr), 0, ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_ERR_ARG
+    assert gpcg.status_string(gpcg.GPCG_ERR_NOT_SPD).startswith("operator")

@@ -1,0 +1,96 @@
+"""Building blocks of the HIP path against the oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import instances
+import oracle
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 37, 50, 129]
+
+
+def _inst(N, op, seed=0):
+    if op == instances.OP_VAR:
+        return instances.varcoef(N, seed)
+    return instances.obstacle(N, seed)
+
+
+@pytest.mark.parametrize("N", SIZES)
+@pytest.mark.parametrize("kind", ["const", "var", "csr"])
+def test_spmv_fp64(N, kind):
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    base = instances.OP_VAR if kind == "var" else instances.OP_CONST
+    inst = _inst(N, base)
+    print(f"spmv fp64 N={N} kind={kind}", flush=True)
+    s = gpcg.Solver(G.operator_for(inst, kind), device=dev)
+    rng = np.random.default_rng(N)
+    v = rng.standard_normal(inst.n)
+    ref = oracle.default().matvec(inst.csr(), v)
+    vd = G.to_dev(v)
+    y = torch.empty_like(vd)
+    s.spmv(vd, y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    scale = np.abs(inst.csr()[2]).max() * np.abs(v).max()
+    assert np.abs(got - ref).max() <= 1e-14 * scale * 8
+    mask = (rng.uniform(size=inst.n) < 0.6).astype(np.uint8)
+    s.spmv(vd, y, G.to_dev(mask))
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    assert np.all(got[mask == 0] == 0.0)
+    assert np.abs(got - ref * mask).max() <= 1e-14 * scale * 8
+    s.close()
+
+
+@pytest.mark.parametrize("kind", ["const", "var", "csr"])
+def test_spmv_fp32(kind):
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    base = instances.OP_VAR if kind == "var" else instances.OP_CONST
+    inst = _inst(61, base)
+    s = gpcg.Solver(G.operator_for(inst, kind), device=dev, precision=gpcg.GPCG_PREC_MIXED)
+    v = np.random.default_rng(1).standard_normal(inst.n).astype(np.float32)
+    ref = oracle.default().matvec(inst.csr(), v.astype(np.float64))
+    vd = G.to_dev(v)
+    y = torch.empty_like(vd)
+    s.spmv(vd, y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    scale = np.abs(inst.csr()[2]).max() * np.abs(v).max()
+    assert np.abs(got - ref).max() <= 1e-5 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 5000, 70001])
+def test_projected_gradient_exact(n):
+    """Projected gradient and face counts are compare/select work: bit-exact."""
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    rng = np.random.default_rng(n)
+    a, c = rng.standard_normal(n), rng.standard_normal(n)
+    l, u = np.minimum(a, c), np.maximum(a, c)
+    l[rng.uniform(size=n) < 0.1] = -np.inf
+    u[rng.uniform(size=n) < 0.1] = np.inf
+    fx = rng.uniform(size=n) < 0.05
+    u[fx] = l[fx]
+    x = np.clip(rng.standard_normal(n), l, u)
+    pick = rng.uniform(size=n)
+    x = np.where(pick < 0.3, np.where(np.isfinite(l), l, x), x)
+    x = np.where(pick > 0.8, np.where(np.isfinite(u), u, x), x)
+    g = rng.standard_normal(n)
+    g[rng.uniform(size=n) < 0.05] = 0.0
+    ora = oracle.default()
+    inst = instances.obstacle(1, 0)
+    s = gpcg.Solver(gpcg.Operator.csr(G.to_dev(np.arange(n + 1, dtype=np.int32)),
+                                      G.to_dev(np.arange(n, dtype=np.int32)),
+                                      G.to_dev(np.ones(n))), device=dev)
+    pg = torch.empty(n, dtype=torch.float64, device=dev)
+    n2, lo, up, nb = s.projected_gradient(G.to_dev(x), G.to_dev(l), G.to_dev(u), G.to_dev(g), pg)
+    want = ora.proj_gradient(x, l, u, g)
+    assert np.array_equal(pg.cpu().numpy(), want)
+    assert (lo, up, nb) == ora.classify(x, l, u, g)
+    assert np.isclose(n2, np.sum(want * want), rtol=1e-13)
+    s.close()

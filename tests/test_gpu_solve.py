@@ -1,0 +1,180 @@
+"""Whole GPCG solves on the GPU against the FP64 oracle (through the C ABI).
+
+Parity bar: ||x - x*||_inf / ||x*||_inf <= 1e-8 (FP64 form) and <= 1e-6 (mixed
+form) against the polished oracle solution x*, with identical active sets
+outside the degenerate set (free variables within 1e-10 of a bound, active
+variables with |g| within 1e-10 of zero).  The claim is made at a projected-
+gradient tolerance tight enough for it to follow: on the face of x*,
+||x - x*||_2 <= ||P grad q(x)||_2 / lambda_min(A) with lambda_min ~ 2 pi^2 for
+both grid operators, so tol_rel = 1e-12 suffices for every instance here.
+"""
+import numpy as np
+import pytest
+
+import instances
+import oracle
+from oracle import exact
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-12
+_REF = {}
+
+
+def reference(name, inst):
+    """Polished x* (oracle GPCG at a tight tolerance, then exact face solve)."""
+    if name not in _REF:
+        xo, go, st = oracle.default().solve_instance(inst, tol_rel=1e-12)
+        xs, info = exact.polish(inst.csr(), inst.b, inst.l, inst.u, xo)
+        assert info["converged"] and info["kkt"] < 1e-8 * max(1.0, np.abs(inst.b).max())
+        A = exact.csr_matrix(inst.csr())
+        _REF[name] = (xs, A @ xs - inst.b, st)
+    return _REF[name]
+
+
+def check_faces(x, xs, gs, inst):
+    deg = exact.degenerate_set(xs, gs, inst.l, inst.u)
+    act_gpu = (x == inst.l) | (x == inst.u)
+    act_ref = (xs == inst.l) | (xs == inst.u)
+    bad = (act_gpu != act_ref) & ~deg
+    assert not bad.any(), f"{bad.sum()} active-set mismatches off the degenerate set"
+
+
+def cpu_projected_gradient_norm(inst, x):
+    ora = oracle.default()
+    g = ora.gradient(inst.csr(), x, inst.b)
+    return ora.proj_gradient_norm(x, inst.l, inst.u, g)
+
+
+CASES = [
+    ("c0", lambda: instances.config0(0), None),
+    ("c0_csr", lambda: instances.config0(0), "csr"),
+    ("c1", lambda: instances.config1(0), None),
+    ("c1_csr", lambda: instances.config1(0), "csr"),
+    ("obst_ragged", lambda: instances.obstacle(77, 3, amplitude=0.45, u_random=True), None),
+]
+
+
+@pytest.mark.parametrize("name,make,kind", CASES, ids=[c[0] for c in CASES])
+def test_fp64_matches_oracle(name, make, kind):
+    inst = make()
+    print(f"solve fp64 {name} n={inst.n}", flush=True)
+    xs, gs, st_ref = reference(name.split("_csr")[0], inst)
+    x, g, st = G.solve(inst, kind, tol_rel=TIGHT)
+    assert st["status"] == 0, st
+    assert np.all(x >= inst.l) and np.all(x <= inst.u)
+    err = G.rel_inf(x, xs)
+    print(f"  outer={st['outer_iters']} gp={st['gp_iters']} cg={st['cg_iters']} err={err:.2e} "
+          f"(oracle outer={st_ref['outer_iters']} cg={st_ref['cg_iters']})", flush=True)
+    assert err <= 1e-8
+    check_faces(x, xs, gs, inst)
+    # the returned gradient is g = Ax - b at the answer
+    A = exact.csr_matrix(inst.csr())
+    assert np.allclose(g, A @ x - inst.b, rtol=0, atol=1e-9 * np.abs(inst.b).max() + 1e-12)
+
+
+@pytest.mark.parametrize("name,make", [("c0", lambda: instances.config0(0)),
+                                       ("c1", lambda: instances.config1(0))])
+def test_metric_tolerance_holds_on_cpu(name, make):
+    """At the metric tolerance (1e-8 relative) the answer satisfies the
+    termination test when its projected gradient is recomputed on the CPU."""
+    inst = make()
+    x, g, st = G.solve(inst)
+    assert st["status"] == 0
+    pg = cpu_projected_gradient_norm(inst, x)
+    assert pg <= st["tau"] * 1.001 + 1e-14, (pg, st["tau"])
+    xs, gs, _ = reference(name, inst)
+    print(f"  metric tol: err vs x* = {G.rel_inf(x, xs):.2e}", flush=True)
+
+
+def test_mixed_precision_matches_oracle():
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.config1(0)
+    xs, gs, _ = reference("c1", inst)
+    x, g, st = G.solve(inst, precision=gpcg.GPCG_PREC_MIXED, tol_rel=1e-10)
+    err = G.rel_inf(x, xs)
+    print(f"  mixed: status={st['status']} outer={st['outer_iters']} cg={st['cg_iters']} "
+          f"err={err:.2e}", flush=True)
+    assert st["status"] == 0
+    assert err <= 1e-6
+    check_faces(x, xs, gs, inst)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny_brute_force(seed):
+    n = 1 + seed % 8
+    inst = instances.tiny_dense(n, seed=500 + seed)
+    ref = exact.brute_force(inst.dense, inst.b, inst.l, inst.u)
+    x, g, st = G.solve(inst, "csr", tol_rel=1e-13)
+    assert st["status"] == 0, st
+    assert np.abs(x - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("op", [instances.OP_CONST, instances.OP_VAR])
+@pytest.mark.parametrize("N", [24, 100])
+def test_manufactured(op, N):
+    """Known x* with lower- and upper-active variables."""
+    inst = instances.manufactured(N, op, seed=N)
+    xs, status = inst.meta["x_star"], inst.meta["status"]
+    x, g, st = G.solve(inst, tol_rel=1e-13)
+    assert st["status"] == 0, st
+    assert G.rel_inf(x, xs) <= 1e-9
+    assert np.array_equal(x == inst.l, status == 1)
+    assert np.array_equal(x == inst.u, status == 2)
+    assert st["n_upper"] == int(np.sum(status == 2))
+
+
+def test_unconstrained_matches_direct_solve():
+    import scipy.sparse.linalg as spla
+    inst = instances.unconstrained(45, instances.OP_VAR, seed=1)
+    want = spla.spsolve(exact.csr_matrix(inst.csr()).tocsc(), inst.b)
+    x, g, st = G.solve(inst, tol_rel=1e-13)
+    assert st["status"] == 0 and st["gp_iters"] == 1
+    assert G.rel_inf(x, want) <= 1e-9
+
+
+def test_deterministic_and_graph_invariant():
+    inst = instances.config0(2)
+    x1, g1, s1 = G.solve(inst)
+    x2, g2, s2 = G.solve(inst)
+    x3, g3, s3 = G.solve(inst, use_graph=0, chunk=7)
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+    assert np.array_equal(g1, g2) and np.array_equal(g1, g3)
+    for k in ("outer_iters", "gp_iters", "cg_iters", "backtracks", "passes"):
+        assert s1[k] == s2[k] == s3[k], k
+
+
+def test_start_outside_box_is_projected():
+    inst = instances.config0(4)
+    inst.x0 = inst.x0.copy()
+    inst.x0[::5] = 3.0
+    x, g, st = G.solve(inst, tol_rel=TIGHT)
+    assert st["x0_projected"] == 1 and st["status"] == 0
+    xs, gs, _ = reference("c0s4", instances.config0(4))
+    assert G.rel_inf(x, xs) <= 1e-8
+
+
+def test_errors():
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.obstacle(20, 1)
+    bad = instances.obstacle(20, 1)
+    bad.l = bad.l.copy()
+    bad.l[17] = 1.0  # above u = 0.25
+    with pytest.raises(gpcg.GpcgError) as e:
+        G.solve(bad)
+    assert e.value.status == gpcg.GPCG_ERR_BOUNDS
+    nan = instances.obstacle(20, 1)
+    nan.b = nan.b.copy()
+    nan.b[3] = np.nan
+    with pytest.raises(gpcg.GpcgError) as e:
+        G.solve(nan)
+    assert e.value.status == gpcg.GPCG_ERR_NAN
+    neg = instances.tiny_dense(5, 3)
+    neg.dense = -np.eye(5)
+    neg.l, neg.u = np.full(5, -np.inf), np.full(5, np.inf)
+    with pytest.raises(gpcg.GpcgError) as e:
+        G.solve(neg, "csr")
+    assert e.value.status == gpcg.GPCG_ERR_NOT_SPD
+    x, g, st = G.solve(inst, max_outer=1)
+    assert st["status"] == gpcg.GPCG_MAXIT and st["outer_iters"] == 1
