@@ -297,3 +297,67 @@ def status_string(code: int) -> str:
 
 def build_info() -> str:
     return _lib.gpcg_build_info().decode()
+
+
+class Server:
+    """Continuous-batching solve service (gpcg_server_*).
+
+    Requests are admitted by arena footprint and free slots while others are
+    running; each request's state stays resident in the arena until done.
+    """
+
+    def __init__(self, arena_bytes: int, max_slots: int, precision=GPCG_PREC_MIXED,
+                 tol_rel=1e-8, quantum=0, device="cuda", stream=None):
+        self._arena, ptr = _workspace(arena_bytes, device)
+        self.opt = gpcg_server_options(arena=ptr, arena_bytes=arena_bytes, max_slots=max_slots,
+                                       precision=precision, tol_rel=tol_rel, quantum=quantum)
+        h = C.c_void_p()
+        check(_lib.gpcg_server_create(C.byref(self.opt), _stream_ptr(stream), C.byref(h)),
+              "gpcg_server_create")
+        self.handle = h
+        self._pending = {}
+
+    @staticmethod
+    def footprint(op: Operator, precision=GPCG_PREC_MIXED) -> int:
+        nbytes = C.c_size_t()
+        check(_lib.gpcg_server_footprint(C.byref(op.desc), precision, C.byref(nbytes)),
+              "gpcg_server_footprint")
+        return nbytes.value
+
+    def submit(self, tag: int, op: Operator, b, l, u, x0, x_out) -> int:
+        """Queues a request; returns the C status (GPCG_ERR_NOSPACE if it can
+        never fit).  The tensors are kept alive until completion."""
+        req = gpcg_request(op=op.desc, b=_dptr(b), l=_dptr(l), u=_dptr(u), x0=_dptr(x0),
+                           x_out=_dptr(x_out), tag=tag)
+        rc = _lib.gpcg_server_submit(self.handle, C.byref(req))
+        if rc == GPCG_OK:
+            self._pending[tag] = (op, b, l, u, x0, x_out)
+        return rc
+
+    def step(self) -> int:
+        active = C.c_int()
+        check(_lib.gpcg_server_step(self.handle, C.byref(active)), "gpcg_server_step")
+        return active.value
+
+    def poll(self, max_items: int = 256):
+        buf = (gpcg_completion * max_items)()
+        got = C.c_int()
+        check(_lib.gpcg_server_poll(self.handle, buf, max_items, C.byref(got)), "gpcg_server_poll")
+        out = []
+        for i in range(got.value):
+            c = buf[i]
+            out.append(dict(tag=c.tag, status=c.status, stats=c.stats.as_dict(),
+                            t_submit=c.t_submit, t_admit=c.t_admit, t_done=c.t_done))
+            self._pending.pop(c.tag, None)
+        return out
+
+    def close(self):
+        if self.handle:
+            _lib.gpcg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
