@@ -1,25 +1,34 @@
 // gpcg_kernels.hip -- HIP kernels of the GPCG hot path for gfx950 (CDNA4).
 //
-// One kernel, `step_kernel`, executes one *pass* of Algorithm GPCG (Section 3
-// of the paper) for every QP of a launch.  A pass is a bandwidth-bound sweep
-// over the unknowns: the operator (five-point stencil with constant or edge
-// weights, or CSR) is applied row by row to a vector that is either loaded or
-// computed on the fly from x, g, l, u (a projected-gradient direction or a
-// trial step), fused with the elementwise updates and with the dot products
-// the pass needs.  Reductions are deterministic: each workgroup reduces its
-// tile with wave64 shuffles and LDS into a fixed slot, and the last workgroup
-// to arrive sums the slots in tile order.  That workgroup then runs the
-// scalar transition of the GPCG state machine (which pass comes next, the
-// step lengths, the stop tests eqs. (pgstop1), (pgstop2), (cgstop1),
-// (cgstop3) and the termination test (bqp_approximate_sol)).
+// A pass of Algorithm GPCG (Section 3 of the paper) is one bandwidth-bound
+// sweep over the unknowns: the operator (five-point stencil with constant or
+// edge weights, or CSR) is applied row by row to vectors that are loaded or
+// computed on the fly from x, g, l, u, fused with the elementwise updates and
+// with every dot product the pass needs.  Passes:
+//   INIT      x = P[x0], g = Ax - b, input checks, ||P grad q||^2, face counts
+//   GP_ALPHA  d = P grad q(y): d'd, d'Ad (exact step, eq. (bqpls))
+//   GP_TRIAL  y' = P[y - alpha g], g' = Ay' - b, written to the spare copies of
+//             x and g; g's, s'As, active-set changes, face of y'.  Accepting
+//             the step (eq. (gplsstop)) is a flip of the current copy.
+//   CG_INIT   free mask, rho = -g on F, u = A rho, w = 0  (eqs. (cg), (cg2))
+//   CG_ITER   one CG iteration in the single-reduction form of Chronopoulos
+//             and Gear: p, s = Ap by recurrence, w, rho, u = A rho, rho'rho,
+//             rho'u (eq. (cgstop1) uses 1/2 alpha rho'rho)
+//   PS_TRIAL  x' = P[x + alpha w], g' = Ax' - b, g's, s'As, face of x'
+//             (eq. (cglsstop2)); acceptance is again a flip.
+// Reductions are deterministic: wave64 butterflies and LDS per tile into a
+// fixed slot, then a fixed-order sum over the slots.  The stepped form sums
+// the slots of the previous launch in every workgroup and runs the scalar
+// transition redundantly (identical inputs, identical decisions), so the
+// kernel boundary is the only barrier and no atomics are used.
 //
-// No MFMA: nothing on this path is a dense contraction.  Memory traffic is the
-// bound; see the per-pass byte counts in the runtime.
+// No MFMA: nothing on this path is a dense contraction; memory traffic bounds
+// every pass.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "gpcg.h"
 #include "gpcg_internal.h"
-#include "../../include/gpcg.h"
 
 namespace gpcg {
 
@@ -50,8 +59,8 @@ __device__ __forceinline__ double proj_grad(double x, double l, double u, double
 }
 
 // Trial points of the two projected searches: P[y - alpha g] (eq. next-y) and
-// P[x + alpha w] (eq. cglsstop2).  Written once so that every workgroup that
-// needs the value at index j (owner or stencil neighbour) gets the same bits.
+// P[x + alpha w] (eq. cglsstop2).  One definition, so that every workgroup
+// evaluating index j (owner or stencil neighbour) gets the same bits.
 __device__ __forceinline__ double gp_point(double y, double l, double u, double g, double a) {
   return mid3(l, u, __fma_rn(-a, g, y));
 }
@@ -71,8 +80,7 @@ template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float
 
 template <typename T>
 struct OpView {
-  int32_t kind, nx, ny;
-  int32_t shift;
+  int32_t kind, nx, ny, shift;
   uint64_t magic;
   T w;
   const T *wx, *wy;
@@ -81,23 +89,23 @@ struct OpView {
 };
 
 template <typename T>
-__device__ __forceinline__ OpView<T> op_view(const QPState *q);
+__device__ __forceinline__ OpView<T> op_view(const QPStatic *S);
 
 template <>
-__device__ __forceinline__ OpView<double> op_view<double>(const QPState *q) {
+__device__ __forceinline__ OpView<double> op_view<double>(const QPStatic *S) {
   OpView<double> A;
-  A.kind = q->op_kind; A.nx = q->nx; A.ny = q->ny; A.shift = q->div_shift; A.magic = q->div_magic;
-  A.w = q->w; A.wx = q->wx; A.wy = q->wy; A.rowptr = q->rowptr; A.colind = q->colind;
-  A.vals = q->vals;
+  A.kind = S->op_kind; A.nx = S->nx; A.ny = S->ny; A.shift = S->div_shift;
+  A.magic = S->div_magic; A.w = S->w; A.wx = S->wx; A.wy = S->wy;
+  A.rowptr = S->rowptr; A.colind = S->colind; A.vals = S->vals;
   return A;
 }
 
 template <>
-__device__ __forceinline__ OpView<float> op_view<float>(const QPState *q) {
+__device__ __forceinline__ OpView<float> op_view<float>(const QPStatic *S) {
   OpView<float> A;
-  A.kind = q->op_kind; A.nx = q->nx; A.ny = q->ny; A.shift = q->div_shift; A.magic = q->div_magic;
-  A.w = q->w32; A.wx = q->wx32; A.wy = q->wy32; A.rowptr = q->rowptr; A.colind = q->colind;
-  A.vals = q->vals32;
+  A.kind = S->op_kind; A.nx = S->nx; A.ny = S->ny; A.shift = S->div_shift;
+  A.magic = S->div_magic; A.w = S->w32; A.wx = S->wx32; A.wy = S->wy32;
+  A.rowptr = S->rowptr; A.colind = S->colind; A.vals = S->vals32;
   return A;
 }
 
@@ -127,6 +135,47 @@ __device__ __forceinline__ T apply_row(const OpView<T> &A, int64_t k, F v) {
   return (wW * (c - vW) + wE * (c - vE)) + (wS * (c - vS) + wN * (c - vN));
 }
 
+struct Pair {
+  double y, s;
+};
+
+// Row k of A applied to two vectors at once (a trial point y and its step
+// s = y - x): returns (A y)_k and (A s)_k from one evaluation per entry.
+template <class F>
+__device__ __forceinline__ Pair apply_row2(const OpView<double> &A, int64_t k, F v) {
+  Pair r{0.0, 0.0};
+  if (A.kind == OPK_CSR) {
+    const int32_t e0 = A.rowptr[k], e1 = A.rowptr[k + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+      const Pair t = v((int64_t)A.colind[e]);
+      const double a = A.vals[e];
+      r.y = __fma_rn(a, t.y, r.y);
+      r.s = __fma_rn(a, t.s, r.s);
+    }
+    return r;
+  }
+  const int32_t nx = A.nx;
+  const int32_t j = (int32_t)(((uint64_t)k * A.magic) >> A.shift);
+  const int32_t i = (int32_t)(k - (int64_t)j * nx);
+  const Pair z{0.0, 0.0};
+  const Pair c = v(k);
+  const Pair W = i > 0 ? v(k - 1) : z;
+  const Pair E = i < nx - 1 ? v(k + 1) : z;
+  const Pair So = j > 0 ? v(k - nx) : z;
+  const Pair No = j < A.ny - 1 ? v(k + nx) : z;
+  if (A.kind == OPK_CONST) {
+    r.y = A.w * ((c.y - W.y) + (c.y - E.y) + ((c.y - So.y) + (c.y - No.y)));
+    r.s = A.w * ((c.s - W.s) + (c.s - E.s) + ((c.s - So.s) + (c.s - No.s)));
+    return r;
+  }
+  const int64_t ex = (int64_t)j * (nx + 1) + i;
+  const int64_t ey = (int64_t)j * nx + i;
+  const double wW = A.wx[ex], wE = A.wx[ex + 1], wS = A.wy[ey], wN = A.wy[ey + nx];
+  r.y = (wW * (c.y - W.y) + wE * (c.y - E.y)) + (wS * (c.y - So.y) + wN * (c.y - No.y));
+  r.s = (wW * (c.s - W.s) + wE * (c.s - E.s)) + (wS * (c.s - So.s) + wN * (c.s - No.s));
+  return r;
+}
+
 // ---------------------------------------------------------------- reductions
 
 // Sum of N values over the workgroup; the result is valid in thread 0.  The
@@ -151,7 +200,7 @@ __device__ __forceinline__ void block_sum(R (&v)[N]) {
 
 // Map the launch index of a workgroup to a tile so that consecutive tiles land
 // on the same XCD: gfx950 dispatches workgroups round-robin over its 8 XCDs,
-// each with its own L2, and stencil neighbours of a tile live in the tiles
+// each with its own L2, and the stencil neighbours of a tile live in the tiles
 // next to it.
 __device__ __forceinline__ int xcd_tile(int b, int G) {
   constexpr int X = 8;
@@ -160,69 +209,106 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
-// Which reduction type a pass uses: FP32 for the CG passes of the mixed form.
-__device__ __forceinline__ bool f32_pass(int mixed, int phase) {
-  return mixed && (phase == PH_CG_INIT || phase == PH_CG_A || phase == PH_CG_B);
+// Slots 0 and 1 of the CG passes are FP32 sums in the mixed form.
+__device__ __forceinline__ bool f32_slots(int mixed, int phase) {
+  return mixed && (phase == PH_CG_INIT || phase == PH_CG_ITER);
 }
 
-// ------------------------------------------------------------------- passes
-
-template <typename CT>
-struct Vecs {
-  CT *w, *r, *pold, *pnew;
-};
-
-template <typename CT>
-__device__ __forceinline__ Vecs<CT> cg_vecs(const QPState *q) {
-  Vecs<CT> V;
-  V.w = (CT *)q->vw;
-  V.r = (CT *)q->vr;
-  CT *p0 = (CT *)q->vp0, *p1 = (CT *)q->vp1;
-  V.pold = q->pcur ? p1 : p0;
-  V.pnew = q->pcur ? p0 : p1;
-  return V;
+// Reduces this workgroup's per-thread sums into partials[tile] (thread 0).
+__device__ __forceinline__ void write_partial(double *part, bool f32, int tile, double (&acc)[kNP],
+                                              float (&accf)[2]) {
+  block_sum<double, kNP>(acc);
+  if (f32) {
+    block_sum<float, 2>(accf);
+    if (threadIdx.x == 0) {
+      acc[0] = (double)accf[0];
+      acc[1] = (double)accf[1];
+    }
+  }
+  if (threadIdx.x == 0) {
+    double *slot = part + (int64_t)tile * kNP;
+#pragma unroll
+    for (int k = 0; k < kNP; ++k) slot[k] = acc[k];
+  }
 }
 
-// One pass over the unknowns [k0, k1) of QP q; fills acc (this thread's part).
+// Sums the ntiles slots of `part` in tile order; result in thread 0's res.
+__device__ __forceinline__ void sum_partials(const double *part, int ntiles, bool f32,
+                                             double (&res)[kNP]) {
+  double v[kNP];
+  float vf[2] = {0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < kNP; ++k) v[k] = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += kBlock) {
+    const double *slot = part + (int64_t)t * kNP;
+#pragma unroll
+    for (int k = 0; k < kNP; ++k) v[k] += slot[k];
+    vf[0] += (float)slot[0];
+    vf[1] += (float)slot[1];
+  }
+  block_sum<double, kNP>(v);
+  if (f32) {
+    block_sum<float, 2>(vf);
+    if (threadIdx.x == 0) {
+      v[0] = (double)vf[0];
+      v[1] = (double)vf[1];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kNP; ++k) res[k] = v[k];
+}
+
+// ------------------------------------------------------------ the passes
+
+// Face of a point: ||P grad q||^2, lower-active, upper-active, active and not
+// binding, and x'(g - b) (twice q(x)).
+__device__ __forceinline__ void face_acc(double x, double l, double u, double g, double b,
+                                         double (&acc)[kNP]) {
+  const double p = proj_grad(x, l, u, g);
+  acc[0] = __fma_rn(p, p, acc[0]);
+  acc[1] += (x == l) ? 1.0 : 0.0;
+  acc[2] += (x != l && x == u) ? 1.0 : 0.0;
+  acc[3] += (is_active(x, l, u) && !is_binding(x, l, u, g)) ? 1.0 : 0.0;
+  acc[4] = __fma_rn(x, g - b, acc[4]);
+}
+
 template <typename CT>
-__device__ void run_pass(const QPState *__restrict__ q, int phase, int64_t k0, int64_t k1,
-                         double (&acc)[kNP], float (&accf)[kNP]) {
-  const double *__restrict__ l = q->l;
-  const double *__restrict__ u = q->u;
-  const double *__restrict__ b = q->b;
-  double *__restrict__ x = q->x;
-  double *__restrict__ g = q->g;
-  const int64_t s = kBlock;
+__device__ void run_pass(const QPStatic *__restrict__ S, const QPDyn &d, int phase, int64_t k0,
+                         int64_t k1, double (&acc)[kNP], float (&accf)[2]) {
+  const double *__restrict__ l = S->l;
+  const double *__restrict__ u = S->u;
+  const double *__restrict__ b = S->b;
+  const int c = d.cur;
+  const double *__restrict__ x = S->x[c];
+  const double *__restrict__ g = S->g[c];
+  double *__restrict__ xn = S->x[c ^ 1];
+  double *__restrict__ gn = S->g[c ^ 1];
+  constexpr int64_t st = kBlock;
   switch (phase) {
-    case PH_PROJECT: {
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
-        const double x0 = x[k], lk = l[k], uk = u[k], bk = b[k];
-        acc[1] += (isnan(x0) || isnan(lk) || isnan(uk) || isnan(bk)) ? 1.0 : 0.0;
-        acc[0] += (lk > uk) ? 1.0 : 0.0;
-        const double xn = mid3(lk, uk, x0);
-        acc[2] += (xn != x0) ? 1.0 : 0.0;
-        x[k] = xn;
-      }
-    } break;
-    case PH_GRAD: {
-      const OpView<double> A = op_view<double>(q);
-      auto xv = [&](int64_t j) { return x[j]; };
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
-        const double xk = x[k], lk = l[k], uk = u[k], bk = b[k];
+    case PH_INIT: {
+      // x[0] holds x0; it is projected in place.  A neighbour may read x0_j
+      // before or after its owner projects it: mid(l, u, .) is idempotent, so
+      // both give the same value (l <= u is verified by this same pass).
+      const OpView<double> A = op_view<double>(S);
+      double *x0 = S->x[0];
+      double *__restrict__ g0 = S->g[0];
+      auto xv = [&](int64_t j) { return mid3(l[j], u[j], x0[j]); };
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
+        const double xo = x0[k], lk = l[k], uk = u[k], bk = b[k];
+        const double xk = mid3(lk, uk, xo);
         const double gk = apply_row<double>(A, k, xv) - bk;
-        g[k] = gk;
-        const double pg = proj_grad(xk, lk, uk, gk);
-        acc[0] = __fma_rn(pg, pg, acc[0]);
-        acc[1] += (xk == lk) ? 1.0 : 0.0;
-        acc[2] += (xk != lk && xk == uk) ? 1.0 : 0.0;
-        acc[3] += (is_active(xk, lk, uk) && !is_binding(xk, lk, uk, gk)) ? 1.0 : 0.0;
-        acc[4] = __fma_rn(xk, gk - bk, acc[4]);
+        acc[5] += (lk > uk) ? 1.0 : 0.0;
+        acc[6] += (isnan(xo) || isnan(lk) || isnan(uk) || isnan(bk)) ? 1.0 : 0.0;
+        acc[7] += (xk != xo) ? 1.0 : 0.0;
+        x0[k] = xk;
+        g0[k] = gk;
+        face_acc(xk, lk, uk, gk, bk, acc);
       }
     } break;
     case PH_GP_ALPHA: {
-      const OpView<double> A = op_view<double>(q);
+      const OpView<double> A = op_view<double>(S);
       auto dv = [&](int64_t j) { return proj_grad(x[j], l[j], u[j], g[j]); };
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
         const double dk = dv(k);
         const double Adk = apply_row<double>(A, k, dv);
         acc[0] = __fma_rn(dk, dk, acc[0]);
@@ -230,108 +316,136 @@ __device__ void run_pass(const QPState *__restrict__ q, int phase, int64_t k0, i
       }
     } break;
     case PH_GP_TRIAL: {
-      const OpView<double> A = op_view<double>(q);
-      const double a = q->alpha;
-      auto sv = [&](int64_t j) {
-        const double yj = x[j];
-        return gp_point(yj, l[j], u[j], g[j], a) - yj;
+      const OpView<double> A = op_view<double>(S);
+      const double a = d.alpha;
+      auto yv = [&](int64_t j) {
+        const double xj = x[j];
+        const double yj = gp_point(xj, l[j], u[j], g[j], a);
+        return Pair{yj, yj - xj};
       };
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
-        const double yk = x[k], lk = l[k], uk = u[k], gk = g[k];
-        const double yn = gp_point(yk, lk, uk, gk, a);
-        const double sk = yn - yk;
-        const double Ask = apply_row<double>(A, k, sv);
-        acc[0] = __fma_rn(gk, sk, acc[0]);
-        acc[1] = __fma_rn(sk, Ask, acc[1]);
-        acc[2] += (is_active(yn, lk, uk) != is_active(yk, lk, uk)) ? 1.0 : 0.0;
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
+        const double xk = x[k], lk = l[k], uk = u[k], gk = g[k], bk = b[k];
+        const double yk = gp_point(xk, lk, uk, gk, a);
+        const double sk = yk - xk;
+        const Pair As = apply_row2(A, k, yv);
+        const double gy = As.y - bk;
+        xn[k] = yk;
+        gn[k] = gy;
+        face_acc(yk, lk, uk, gy, bk, acc);
+        acc[5] = __fma_rn(gk, sk, acc[5]);
+        acc[6] = __fma_rn(sk, As.s, acc[6]);
+        acc[7] += (is_active(yk, lk, uk) != is_active(xk, lk, uk)) ? 1.0 : 0.0;
       }
-    } break;
-    case PH_GP_ACCEPT: {
-      const double a = q->alpha;
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) x[k] = gp_point(x[k], l[k], u[k], g[k], a);
     } break;
     case PH_CG_INIT: {
-      const Vecs<CT> V = cg_vecs<CT>(q);
-      CT *p0 = (CT *)q->vp0, *p1 = (CT *)q->vp1;
-      uint8_t *mask = q->mask;
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
+      const OpView<CT> A = op_view<CT>(S);
+      uint8_t *__restrict__ mask = S->mask;
+      CT *__restrict__ r0 = (CT *)S->rho[0];
+      CT *__restrict__ u0 = (CT *)S->uq[0];
+      CT *__restrict__ r1 = (CT *)S->rho[1];
+      CT *__restrict__ u1 = (CT *)S->uq[1];
+      CT *__restrict__ s0 = (CT *)S->sq[0];
+      CT *__restrict__ s1 = (CT *)S->sq[1];
+      CT *__restrict__ p = (CT *)S->pv;
+      CT *__restrict__ w = (CT *)S->wv;
+      auto rv = [&](int64_t j) {
+        const double xj = x[j];
+        return (l[j] < xj && xj < u[j]) ? (CT)(-g[j]) : CT(0);
+      };
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
         const double xk = x[k];
         const bool fr = l[k] < xk && xk < u[k];
-        const CT rk = fr ? (CT)(-g[k]) : CT(0);
         mask[k] = fr ? 1 : 0;
-        V.r[k] = rk;
-        V.w[k] = CT(0);
-        if (!fr) {
-          p0[k] = CT(0);
-          p1[k] = CT(0);
+        if (fr) {
+          const CT rk = (CT)(-g[k]);
+          const CT uk = apply_row<CT>(A, k, rv);
+          r0[k] = rk;
+          u0[k] = uk;
+          w[k] = CT(0);
+          if (sizeof(CT) == 4) {
+            accf[0] = fmaT<float>((float)rk, (float)rk, accf[0]);
+            accf[1] = fmaT<float>((float)rk, (float)uk, accf[1]);
+          } else {
+            acc[0] = __fma_rn((double)rk, (double)rk, acc[0]);
+            acc[1] = __fma_rn((double)rk, (double)uk, acc[1]);
+          }
+          acc[2] += 1.0;
+        } else {
+          // neighbours read these on the active set: keep them zero
+          r0[k] = CT(0);
+          u0[k] = CT(0);
+          r1[k] = CT(0);
+          u1[k] = CT(0);
+          s0[k] = CT(0);
+          s1[k] = CT(0);
+          p[k] = CT(0);
         }
-        if (sizeof(CT) == 4) accf[0] = fmaT<float>((float)rk, (float)rk, accf[0]);
-        else acc[0] = __fma_rn((double)rk, (double)rk, acc[0]);
-        acc[1] += fr ? 1.0 : 0.0;
       }
     } break;
-    case PH_CG_A: {
-      const OpView<CT> A = op_view<CT>(q);
-      const Vecs<CT> V = cg_vecs<CT>(q);
-      const uint8_t *mask = q->mask;
-      const bool first = q->first_cg != 0;
-      const CT beta = (CT)q->beta;
-      auto pn = [&](int64_t j) { return first ? V.r[j] : fmaT<CT>(beta, V.pold[j], V.r[j]); };
-      CT sum = CT(0);
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
-        if (!mask[k]) continue;  // r, w, p are zero on the active set
-        const CT pk = pn(k);
-        V.pnew[k] = pk;
-        const CT Apk = apply_row<CT>(A, k, pn);
-        sum = fmaT<CT>(pk, Apk, sum);
+    case PH_CG_ITER: {
+      const OpView<CT> A = op_view<CT>(S);
+      const uint8_t *__restrict__ mask = S->mask;
+      const int par = d.cgpar;
+      const bool first = d.first != 0;
+      const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
+      const CT *__restrict__ ro = (const CT *)S->rho[par];
+      const CT *__restrict__ uo = (const CT *)S->uq[par];
+      const CT *__restrict__ so = (const CT *)S->sq[par];
+      CT *__restrict__ rn = (CT *)S->rho[par ^ 1];
+      CT *__restrict__ un = (CT *)S->uq[par ^ 1];
+      CT *__restrict__ sn = (CT *)S->sq[par ^ 1];
+      CT *__restrict__ p = (CT *)S->pv;
+      CT *__restrict__ w = (CT *)S->wv;
+      // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i
+      auto snew = [&](int64_t j) { return first ? uo[j] : fmaT<CT>(be, so[j], uo[j]); };
+      auto rnew = [&](int64_t j) { return fmaT<CT>(-al, snew(j), ro[j]); };
+      CT gam = CT(0), del = CT(0);
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
+        if (!mask[k]) continue;  // the CG vectors vanish on the active set
+        const CT rk = ro[k];
+        const CT sk = snew(k);
+        const CT r1 = fmaT<CT>(-al, sk, rk);
+        const CT pk = first ? rk : fmaT<CT>(be, p[k], rk);
+        w[k] = fmaT<CT>(al, pk, w[k]);
+        p[k] = pk;
+        sn[k] = sk;
+        rn[k] = r1;
+        const CT u1 = apply_row<CT>(A, k, rnew);
+        un[k] = u1;
+        gam = fmaT<CT>(r1, r1, gam);
+        del = fmaT<CT>(r1, u1, del);
       }
-      if (sizeof(CT) == 4) accf[0] = (float)sum;
-      else acc[0] = (double)sum;
-    } break;
-    case PH_CG_B: {
-      const OpView<CT> A = op_view<CT>(q);
-      const Vecs<CT> V = cg_vecs<CT>(q);
-      const uint8_t *mask = q->mask;
-      const CT a = (CT)q->cg_alpha;
-      const CT *__restrict__ p = V.pnew;
-      auto pv = [&](int64_t j) { return p[j]; };
-      CT sum = CT(0);
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
-        if (!mask[k]) continue;
-        const CT pk = p[k];
-        const CT Apk = apply_row<CT>(A, k, pv);
-        V.w[k] = fmaT<CT>(a, pk, V.w[k]);
-        const CT rk = fmaT<CT>(-a, Apk, V.r[k]);
-        V.r[k] = rk;
-        sum = fmaT<CT>(rk, rk, sum);
+      if (sizeof(CT) == 4) {
+        accf[0] = (float)gam;
+        accf[1] = (float)del;
+      } else {
+        acc[0] = (double)gam;
+        acc[1] = (double)del;
       }
-      if (sizeof(CT) == 4) accf[0] = (float)sum;
-      else acc[0] = (double)sum;
     } break;
     case PH_PS_TRIAL: {
-      const OpView<double> A = op_view<double>(q);
-      const CT *__restrict__ w = (const CT *)q->vw;
-      const uint8_t *mask = q->mask;
-      const double a = q->alpha;
-      auto sv = [&](int64_t j) {
-        if (!mask[j]) return 0.0;  // the CG direction is zero on A(x_k)
+      const OpView<double> A = op_view<double>(S);
+      const uint8_t *__restrict__ mask = S->mask;
+      const CT *__restrict__ w = (const CT *)S->wv;
+      const double a = d.alpha;
+      // the CG direction is zero on A(x_k): those entries do not move
+      auto yv = [&](int64_t j) {
         const double xj = x[j];
-        return ps_point(xj, l[j], u[j], (double)w[j], a) - xj;
+        const double yj = mask[j] ? ps_point(xj, l[j], u[j], (double)w[j], a) : xj;
+        return Pair{yj, yj - xj};
       };
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s) {
-        if (!mask[k]) continue;
-        const double sk = sv(k);
-        const double Ask = apply_row<double>(A, k, sv);
-        acc[0] = __fma_rn(g[k], sk, acc[0]);
-        acc[1] = __fma_rn(sk, Ask, acc[1]);
+      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
+        const double xk = x[k], lk = l[k], uk = u[k], gk = g[k], bk = b[k];
+        const double yk = mask[k] ? ps_point(xk, lk, uk, (double)w[k], a) : xk;
+        const double sk = yk - xk;
+        const Pair As = apply_row2(A, k, yv);
+        const double gy = As.y - bk;
+        xn[k] = yk;
+        gn[k] = gy;
+        face_acc(yk, lk, uk, gy, bk, acc);
+        acc[5] = __fma_rn(gk, sk, acc[5]);
+        acc[6] = __fma_rn(sk, As.s, acc[6]);
       }
-    } break;
-    case PH_PS_ACCEPT: {
-      const CT *__restrict__ w = (const CT *)q->vw;
-      const uint8_t *mask = q->mask;
-      const double a = q->alpha;
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += s)
-        if (mask[k]) x[k] = ps_point(x[k], l[k], u[k], (double)w[k], a);
     } break;
     default:
       break;
@@ -340,327 +454,278 @@ __device__ void run_pass(const QPState *__restrict__ q, int phase, int64_t k0, i
 
 // ------------------------------------------------------ the scalar transition
 
-__device__ __forceinline__ int time_bucket(int phase, int ctx) {
+__device__ __forceinline__ int time_bucket(int phase) {
   switch (phase) {
-    case PH_CG_INIT: case PH_CG_A: case PH_CG_B: return TB_CG;
-    case PH_GP_ALPHA: case PH_GP_TRIAL: case PH_GP_ACCEPT: return TB_GP;
-    case PH_PS_TRIAL: case PH_PS_ACCEPT: return TB_SEARCH;
-    case PH_GRAD: return ctx == CTX_GP ? TB_GP : (ctx == CTX_PS ? TB_SEARCH : TB_OTHER);
+    case PH_CG_INIT: case PH_CG_ITER: return TB_CG;
+    case PH_GP_ALPHA: case PH_GP_TRIAL: return TB_GP;
+    case PH_PS_TRIAL: return TB_SEARCH;
     default: return TB_OTHER;
   }
 }
 
-__device__ void finish(QPState *q, int status) {
-  q->status = status;
-  q->phase = PH_DONE;
-  if (q->host_flag)
-    __hip_atomic_store(q->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ __forceinline__ void finish(QPDyn &d, int status) {
+  d.status = status;
+  d.phase = PH_DONE;
 }
 
 // A gradient-projection phase begins: y_0 = x_k (Algorithm GPCG, first bullet).
-__device__ void start_gp(QPState *q) {
-  q->gp_j = 1;
-  q->gp_decmax = -INFINITY;
-  q->gp_accepts = 0;
-  q->phase = PH_GP_ALPHA;
+__device__ __forceinline__ void start_gp(QPDyn &d) {
+  d.gp_j = 1;
+  d.gp_decmax = -INFINITY;
+  d.gp_accepts = 0;
+  d.phase = PH_GP_ALPHA;
 }
 
 // The gradient-projection phase ends: termination test, then CG with the
-// initial eta2 (it is reset whenever a gradient-projection phase runs).
-__device__ void end_gp(QPState *q) {
-  if (q->pgn <= q->tau) {
-    finish(q, GPCG_OK);
+// initial eta2 (reset whenever a gradient-projection phase runs).
+__device__ __forceinline__ void end_gp(const QPStatic *S, QPDyn &d) {
+  if (d.pgn <= d.tau) {
+    finish(d, GPCG_OK);
     return;
   }
-  q->eta = q->eta2;
-  q->phase = PH_CG_INIT;
+  d.eta = S->eta2;
+  d.phase = PH_CG_INIT;
 }
 
 // Projected search along d_k = Z_k w: alpha = 1, 1/2, 1/4, ... (eq. cglsstop2).
-__device__ void start_ps(QPState *q) {
-  q->alpha = 1.0;
-  q->bt = 0;
-  q->ps_accepted = 0;
-  q->phase = PH_PS_TRIAL;
+__device__ __forceinline__ void start_ps(QPDyn &d) {
+  d.alpha = 1.0;
+  d.bt = 0;
+  d.ps_accepted = 0;
+  d.phase = PH_PS_TRIAL;
 }
 
-// Runs in one thread after the pass `phase` of QP q has been reduced into r.
-__device__ void transition(QPState *q, int phase, const double *r) {
+__device__ __forceinline__ void set_face(QPDyn &d, const double *R) {
+  d.pgn = sqrt(R[0]);
+  d.n_lower = (int64_t)R[1];
+  d.n_upper = (int64_t)R[2];
+  d.n_nonbinding = (int64_t)R[3];
+  d.q = 0.5 * R[4];
+}
+
+// Folds the reduced results R of pass d.phase into the state and selects the
+// next pass.  Runs in one thread of every workgroup on identical inputs.
+__device__ void transition(const QPStatic *S, QPDyn &d, const double *R) {
+  const int ph = d.phase;
   const uint64_t now = wall_clock64();
-  if (q->t_last) q->t_bucket[time_bucket(phase, q->ctx)] += now - q->t_last;
-  q->t_last = now;
-  q->passes += 1;
-  q->pass_count[phase] += 1;
-  switch (phase) {
-    case PH_PROJECT:
-      if (r[1] > 0.0) { finish(q, GPCG_ERR_NAN); break; }
-      if (r[0] > 0.0) { finish(q, GPCG_ERR_BOUNDS); break; }
-      q->x0_projected = r[2] > 0.0 ? 1 : 0;
-      q->phase = PH_GRAD;
-      q->ctx = CTX_INIT;
+  if (d.t_last) d.t_bucket[time_bucket(ph)] += now - d.t_last;
+  d.t_last = now;
+  d.passes += 1;
+  d.pass_count[ph] += 1;
+  switch (ph) {
+    case PH_INIT:
+      if (R[6] > 0.0) { finish(d, GPCG_ERR_NAN); break; }
+      if (R[5] > 0.0) { finish(d, GPCG_ERR_BOUNDS); break; }
+      d.x0_projected = R[7] > 0.0 ? 1 : 0;
+      set_face(d, R);
+      d.pg0 = d.pgn;
+      d.tau = S->tol_rel * d.pgn > S->tol_abs ? S->tol_rel * d.pgn : S->tol_abs;
+      d.best_pg = d.pgn;
+      d.stall = 0;
+      if (d.pgn <= d.tau) finish(d, GPCG_OK);
+      else start_gp(d);
       break;
-    case PH_GRAD: {
-      q->pgn = sqrt(r[0]);
-      q->n_lower = (int64_t)r[1];
-      q->n_upper = (int64_t)r[2];
-      q->n_nonbinding = (int64_t)r[3];
-      q->q = 0.5 * r[4];
-      if (q->ctx == CTX_INIT) {
-        q->pg0 = q->pgn;
-        double tau = q->tol_abs;
-        if (q->tol_rel * q->pgn > tau) tau = q->tol_rel * q->pgn;
-        q->tau = tau;
-        q->best_pg = q->pgn;
-        q->stall = 0;
-        if (q->pgn <= tau) finish(q, GPCG_OK);
-        else start_gp(q);
-      } else if (q->ctx == CTX_GP) {
-        // y_j accepted and its gradient known: eqs. (pgstop1), (pgstop2)
-        q->gp_iters += 1;
-        q->gp_accepts += 1;
-        const double dec = q->pend_dec;
-        const bool stop = (q->pend_nchg == 0) ||
-                          (q->gp_j >= 2 && dec <= q->eta1 * q->gp_decmax) ||
-                          (q->gp_j >= q->max_gp);
-        if (dec > q->gp_decmax) q->gp_decmax = dec;
-        if (stop) end_gp(q);
-        else {
-          q->gp_j += 1;
-          q->phase = PH_GP_ALPHA;
-        }
-      } else {
-        // x_{k+1} known: termination test, then eq. (cgstop3)
-        q->outer_iters += 1;
-        bool stalled = false;
-        if (q->pgn < q->best_pg) {
-          q->best_pg = q->pgn;
-          q->stall = 0;
-        } else {
-          q->stall += 1;
-          stalled = q->stall >= q->max_stall;
-        }
-        if (q->pgn <= q->tau) finish(q, GPCG_OK);
-        else if (stalled) finish(q, GPCG_STAGNATED);
-        else if (!q->ps_accepted) finish(q, GPCG_STAGNATED);
-        else if (q->outer_iters >= q->max_outer) finish(q, GPCG_MAXIT);
-        else if (q->n_nonbinding != 0) start_gp(q);
-        else {
-          q->eta *= q->eta2_reduce;
-          q->face_repeats += 1;
-          q->phase = PH_CG_INIT;
-        }
-      }
-    } break;
     case PH_GP_ALPHA:
-      if (r[0] == 0.0) finish(q, GPCG_OK);  // P grad q(y) = 0: y solves the QP
-      else if (!(r[1] > 0.0)) finish(q, GPCG_ERR_NOT_SPD);
+      if (R[0] == 0.0) finish(d, GPCG_OK);  // P grad q(y) = 0: y solves the QP
+      else if (!(R[1] > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
       else {
-        q->alpha = r[0] / r[1];  // eq. (bqpls): ||d||^2 / d'Ad
-        q->bt = 0;
-        q->phase = PH_GP_TRIAL;
+        d.alpha = R[0] / R[1];  // eq. (bqpls): ||d||^2 / d'Ad
+        d.bt = 0;
+        d.phase = PH_GP_TRIAL;
       }
       break;
     case PH_GP_TRIAL: {
-      const double delta = r[0] + 0.5 * r[1];  // q(y') - q(y)
-      if (delta <= q->mu * r[0]) {             // eq. (gplsstop)
-        q->pend_dec = -delta;
-        q->pend_nchg = (int64_t)r[2];
-        q->phase = PH_GP_ACCEPT;
+      const double gs = R[5], delta = gs + 0.5 * R[6];  // q(y') - q(y)
+      if (delta <= S->mu * gs) {                         // eq. (gplsstop): accept
+        d.cur ^= 1;
+        set_face(d, R);
+        d.gp_iters += 1;
+        d.gp_accepts += 1;
+        const double dec = -delta;
+        // eqs. (pgstop1), (pgstop2), and the cap on iterates
+        const bool stop = (R[7] == 0.0) || (d.gp_j >= 2 && dec <= S->eta1 * d.gp_decmax) ||
+                          (d.gp_j >= S->max_gp);
+        if (dec > d.gp_decmax) d.gp_decmax = dec;
+        if (stop) end_gp(S, d);
+        else {
+          d.gp_j += 1;
+          d.phase = PH_GP_ALPHA;
+        }
       } else {
-        q->alpha *= 0.5;
-        q->backtracks += 1;
-        q->bt += 1;
-        if (q->bt > q->max_backtrack) end_gp(q);
+        d.alpha *= 0.5;
+        d.backtracks += 1;
+        d.bt += 1;
+        if (d.bt > S->max_backtrack) end_gp(S, d);
       }
     } break;
-    case PH_GP_ACCEPT:
-      q->phase = PH_GRAD;
-      q->ctx = CTX_GP;
-      break;
     case PH_CG_INIT: {
-      q->m_free = (int64_t)r[1];
-      if (q->m_free == 0) {
-        if (q->gp_accepts == 0) finish(q, GPCG_STAGNATED);
-        else start_gp(q);
+      const int64_t m = (int64_t)R[2];
+      if (m == 0) {
+        if (d.gp_accepts == 0) finish(d, GPCG_STAGNATED);
+        else start_gp(d);
         break;
       }
-      q->cg_phases += 1;
-      q->rr = r[0];
-      q->cg_j = 0;
-      q->cg_decmax = -INFINITY;
-      q->max_cg_eff = q->max_cg > 0 ? q->max_cg : (int32_t)q->m_free;
-      q->first_cg = 1;
-      if (q->rr > 0.0) q->phase = PH_CG_A;
-      else start_ps(q);
-    } break;
-    case PH_CG_A:
-      if (!(r[0] > 0.0)) finish(q, GPCG_ERR_NOT_SPD);
+      d.cg_phases += 1;
+      d.m_free = m;
+      d.cg_j = 0;
+      d.cg_decmax = -INFINITY;
+      d.max_cg_eff = S->max_cg > 0 ? S->max_cg : (int32_t)m;
+      d.first = 1;
+      d.cgpar = 0;
+      d.gamma = R[0];
+      if (!(d.gamma > 0.0)) start_ps(d);  // r_k = 0: the CG direction is 0
+      else if (!(R[1] > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
       else {
-        q->cg_alpha = q->rr / r[0];
-        q->phase = PH_CG_B;
-      }
-      q->cg_free_rows += q->m_free;
-      break;
-    case PH_CG_B: {
-      q->cg_j += 1;
-      q->cg_iters += 1;
-      q->cg_free_rows += q->m_free;
-      const double dec = 0.5 * q->cg_alpha * q->rr;  // q_k(w_{j-1}) - q_k(w_j)
-      const bool stop = (r[0] == 0.0) || (q->cg_j >= 2 && dec <= q->eta * q->cg_decmax) ||
-                        (q->cg_j >= q->max_cg_eff);  // eq. (cgstop1)
-      if (dec > q->cg_decmax) q->cg_decmax = dec;
-      q->pcur ^= 1;
-      if (stop) start_ps(q);
-      else {
-        q->beta = r[0] / q->rr;
-        q->rr = r[0];
-        q->first_cg = 0;
-        q->phase = PH_CG_A;
+        d.cg_alpha = d.gamma / R[1];
+        d.cg_beta = 0.0;
+        d.phase = PH_CG_ITER;
       }
     } break;
-    case PH_PS_TRIAL: {
-      q->cg_free_rows += q->m_free;
-      const double delta = r[0] + 0.5 * r[1];
-      if (delta <= q->mu * r[0]) {
-        q->ps_accepted = 1;
-        q->phase = PH_PS_ACCEPT;
-      } else {
-        q->alpha *= 0.5;
-        q->backtracks += 1;
-        q->bt += 1;
-        if (q->bt > q->max_backtrack) {
-          q->ps_accepted = 0;  // x stays; the gradient pass decides
-          q->phase = PH_GRAD;
-          q->ctx = CTX_PS;
+    case PH_CG_ITER: {
+      d.cg_j += 1;
+      d.cg_iters += 1;
+      d.cg_free_rows += d.m_free;  // unknowns this CG pass swept with full traffic
+      const double dec = 0.5 * d.cg_alpha * d.gamma;  // q_k(w_{j-1}) - q_k(w_j)
+      const bool stop = (R[0] == 0.0) || (d.cg_j >= 2 && dec <= d.eta * d.cg_decmax) ||
+                        (d.cg_j >= d.max_cg_eff);  // eq. (cgstop1)
+      if (dec > d.cg_decmax) d.cg_decmax = dec;
+      d.cgpar ^= 1;
+      d.first = 0;
+      if (stop) start_ps(d);
+      else {
+        const double beta = R[0] / d.gamma;
+        const double pAp = R[1] - beta * R[0] / d.cg_alpha;  // p_{j+1}' A p_{j+1}
+        if (!(pAp > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
+        else {
+          d.cg_beta = beta;
+          d.cg_alpha = R[0] / pAp;
+          d.gamma = R[0];
         }
       }
     } break;
-    case PH_PS_ACCEPT:
-      q->cg_free_rows += q->m_free;
-      q->phase = PH_GRAD;
-      q->ctx = CTX_PS;
-      break;
+    case PH_PS_TRIAL: {
+      const double gs = R[5], delta = gs + 0.5 * R[6];
+      const bool acc = delta <= S->mu * gs;
+      if (!acc) {
+        d.alpha *= 0.5;
+        d.backtracks += 1;
+        d.bt += 1;
+        if (d.bt <= S->max_backtrack) break;  // next trial
+      }
+      // the projected search has ended: x_{k+1} is known
+      if (acc) {
+        d.cur ^= 1;
+        set_face(d, R);
+      }
+      d.ps_accepted = acc ? 1 : 0;
+      d.outer_iters += 1;
+      bool stalled = false;
+      if (d.pgn < d.best_pg) {
+        d.best_pg = d.pgn;
+        d.stall = 0;
+      } else {
+        d.stall += 1;
+        stalled = d.stall >= S->max_stall;
+      }
+      if (d.pgn <= d.tau) finish(d, GPCG_OK);
+      else if (stalled || !acc) finish(d, GPCG_STAGNATED);
+      else if (d.outer_iters >= S->max_outer) finish(d, GPCG_MAXIT);
+      else if (d.n_nonbinding != 0) start_gp(d);  // B(x) != A(x)
+      else {                                       // eq. (cgstop3): B(x) = A(x)
+        d.eta *= S->eta2_reduce;
+        d.face_repeats += 1;
+        d.phase = PH_CG_INIT;
+      }
+    } break;
     default:
       break;
   }
 }
 
-// ------------------------------------------------------------ one workgroup
+// --------------------------------------------------------- state transfer
 
-// Reduces this workgroup's share of a tile into partials[tile] (thread 0
-// writes the slot).  The per-tile value does not depend on which workgroup
-// or which launch form computed it.
-__device__ __forceinline__ void tile_partial(QPState *q, bool f32, int tile, double (&acc)[kNP],
-                                             float (&accf)[kNP]) {
-  if (f32) {
-    block_sum<float, kNP>(accf);
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int k = 0; k < kNP; ++k) acc[k] = (double)accf[k];
-  } else {
-    block_sum<double, kNP>(acc);
-  }
-  if (threadIdx.x == 0) {
-    double *slot = q->partials + (int64_t)tile * kNP;
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) slot[k] = acc[k];
-  }
-}
+constexpr int kDynWords = (int)(sizeof(QPDyn) / 4);
+static_assert(sizeof(QPDyn) % 8 == 0, "QPDyn must be a whole number of words");
+static_assert(kDynWords <= kBlock, "QPDyn must fit one word per thread");
 
-// Arrives at the QP's ticket; if this is the last of `expected` arrivals,
-// sums the ntiles slots in tile order and runs the transition.
-// `release_all`: every thread's stores must be visible to other workgroups
-// after the arrival (persistent form); in the stepped form only the slot
-// must be, the kernel boundary publishes the rest.
-__device__ bool arrive(QPState *q, int phase, bool f32, int ntiles, uint32_t expected,
-                       bool release_all) {
-  __shared__ int s_last;
-  if (release_all) __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(&q->ticket, 1u);
-    s_last = (prev == expected - 1) ? 1 : 0;
-    if (s_last) __threadfence();
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  double res[kNP];
-  if (f32) {
-    float v[kNP];
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) v[k] = 0.0f;
-    for (int t = threadIdx.x; t < ntiles; t += kBlock) {
-      const double *slot = q->partials + (int64_t)t * kNP;
-#pragma unroll
-      for (int k = 0; k < kNP; ++k) v[k] += (float)slot[k];
-    }
-    block_sum<float, kNP>(v);
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) res[k] = (double)v[k];
-  } else {
-    double v[kNP];
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) v[k] = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += kBlock) {
-      const double *slot = q->partials + (int64_t)t * kNP;
-#pragma unroll
-      for (int k = 0; k < kNP; ++k) v[k] += slot[k];
-    }
-    block_sum<double, kNP>(v);
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) res[k] = v[k];
-  }
-  if (threadIdx.x == 0) {
-    q->ticket = 0;
-    transition(q, phase, res);
-  }
-  return true;
+__device__ __forceinline__ void copy_dyn(const QPDyn *src, QPDyn *dst) {
+  if (threadIdx.x < kDynWords)
+    reinterpret_cast<uint32_t *>(dst)[threadIdx.x] =
+        reinterpret_cast<const uint32_t *>(src)[threadIdx.x];
 }
 
 // ------------------------------------------------------------------ kernels
 
-// Stepped form: one launch = one pass of every QP; workgroup = one tile.
+// Stepped form: one launch = one pass of every QP of the launch; one
+// workgroup = one tile.  Every workgroup first folds the previous launch's
+// partial sums into its own copy of the state.
 template <typename CT>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
+  __shared__ QPDyn sd;
+  __shared__ int s_fresh_done;
   const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  int lo = 0, hi = L.nqp;
-  while (hi - lo > 1) {
-    const int m = (lo + hi) >> 1;
-    if (L.prefix[m] <= t) lo = m;
-    else hi = m;
+  QPDev *q;
+  int tile;
+  if (L.single) {
+    q = L.single;
+    tile = t;
+  } else {
+    int lo = 0, hi = L.nqp;
+    while (hi - lo > 1) {
+      const int m = (lo + hi) >> 1;
+      if (L.prefix[m] <= t) lo = m;
+      else hi = m;
+    }
+    q = L.qps[lo];
+    tile = t - L.prefix[lo];
   }
-  QPState *q = L.qps[lo];
-  const int tile = t - L.prefix[lo];
-  const int phase = q->phase;
-  if (phase == PH_DONE) return;
-  const int ntiles = q->ntiles;
-  const int64_t k0 = (int64_t)tile * q->tile;
-  int64_t k1 = k0 + q->tile;
-  if (k1 > q->n) k1 = q->n;
-  double acc[kNP];
-  float accf[kNP];
+  const QPStatic *S = &q->st;
+  const int par = L.parity;
+  copy_dyn(&q->dyn[par], &sd);
+  __syncthreads();
+  if (sd.pending) {
+    double R[kNP];
+    sum_partials(S->partials[par], S->ntiles, f32_slots(S->mixed, sd.phase), R);
+    if (threadIdx.x == 0) {
+      transition(S, sd, R);
+      s_fresh_done = sd.phase == PH_DONE;
+      sd.pending = sd.phase == PH_DONE ? 0 : 1;
+    }
+  } else if (threadIdx.x == 0) {
+    s_fresh_done = 0;
+    sd.pending = sd.phase == PH_DONE ? 0 : 1;
+  }
+  __syncthreads();
+  const int phase = sd.phase;
+  if (phase != PH_DONE) {
+    const int64_t k0 = (int64_t)tile * S->tile;
+    const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
+    double acc[kNP];
+    float accf[2] = {0.0f, 0.0f};
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) {
-    acc[k] = 0.0;
-    accf[k] = 0.0f;
+    for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
+    run_pass<CT>(S, sd, phase, k0, k1, acc, accf);
+    write_partial(S->partials[par ^ 1], f32_slots(S->mixed, phase), tile, acc, accf);
   }
-  run_pass<CT>(q, phase, k0, k1, acc, accf);
-  const bool f32 = f32_pass(q->mixed, phase);
-  tile_partial(q, f32, tile, acc, accf);
-  arrive(q, phase, f32, ntiles, (uint32_t)ntiles, false);
+  if (tile == 0) {
+    copy_dyn(&sd, &q->dyn[par ^ 1]);
+    if (threadIdx.x == 0 && s_fresh_done && S->host_flag)
+      __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
-// Persistent form: one cooperative launch runs every QP to completion.  QP q
-// owns the workgroup slots [wg_prefix[q], wg_prefix[q+1]); in each pass a
-// workgroup sweeps the tiles lw, lw + nwg, ... of its QP, then arrives at
-// the QP's ticket.  The last arrival runs the transition and bumps the QP's
-// generation counter, which the other workgroups of that QP wait for.  No
-// barrier spans two QPs, so every QP advances at its own pace.  Every wait
-// is bounded: after spin_limit polls the QP is failed with GPCG_ERR_HANG
-// and the workgroup exits, so the grid always drains.
+// Persistent form (batches of small QPs): one cooperative launch runs every
+// QP to completion.  QP q owns the workgroup slots [wg_prefix[q],
+// wg_prefix[q+1]); a workgroup sweeps the tiles lw, lw + nwg, ... of its QP
+// in every pass, keeps the state in LDS, and meets the other workgroups of
+// its QP at a counter barrier (no barrier spans two QPs).  The tiles and the
+// order of every sum are those of the stepped form, so results are bitwise
+// identical to it.  Every wait is bounded: after spin_limit polls the QP is
+// failed with GPCG_ERR_HANG and the workgroup exits, so the grid drains.
 template <typename CT>
 __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
+  __shared__ QPDyn sd;
+  __shared__ int s_exit;
   const int slot = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   if (slot >= P.wg_total) return;
   int lo = 0, hi = P.nqp;
@@ -669,70 +734,86 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
     if (P.wg_prefix[m] <= slot) lo = m;
     else hi = m;
   }
-  QPState *q = P.qps[lo];
+  QPDev *q = P.qps[lo];
+  const QPStatic *S = &q->st;
   const int lw = slot - P.wg_prefix[lo];
   const int nwg = P.wg_prefix[lo + 1] - P.wg_prefix[lo];
-  __shared__ int s_exit;
-  for (;;) {
-    const int phase = __hip_atomic_load(&q->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (phase == PH_DONE) break;
-    const uint32_t gen =
-        __hip_atomic_load(&q->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int ntiles = q->ntiles;
-    const bool f32 = f32_pass(q->mixed, phase);
-    for (int tile = lw; tile < ntiles; tile += nwg) {
-      const int64_t k0 = (int64_t)tile * q->tile;
-      int64_t k1 = k0 + q->tile;
-      if (k1 > q->n) k1 = q->n;
-      double acc[kNP];
-      float accf[kNP];
-#pragma unroll
-      for (int k = 0; k < kNP; ++k) {
-        acc[k] = 0.0;
-        accf[k] = 0.0f;
-      }
-      run_pass<CT>(q, phase, k0, k1, acc, accf);
-      tile_partial(q, f32, tile, acc, accf);
+  copy_dyn(&q->dyn[0], &sd);
+  if (threadIdx.x == 0) s_exit = 0;
+  __syncthreads();
+  int par = 0;
+  for (uint32_t round = 1;; ++round) {
+    if (sd.pending) {
+      double R[kNP];
+      sum_partials(S->partials[par], S->ntiles, f32_slots(S->mixed, sd.phase), R);
+      if (threadIdx.x == 0) transition(S, sd, R);
+      __syncthreads();
     }
-    const bool last = arrive(q, phase, f32, ntiles, (uint32_t)nwg, true);
-    if (threadIdx.x == 0) {
-      s_exit = 0;
-      if (last) {
-        __threadfence();
-        __hip_atomic_store(&q->generation, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
+    const int phase = sd.phase;
+    if (phase == PH_DONE) break;
+    for (int tile = lw; tile < S->ntiles; tile += nwg) {
+      const int64_t k0 = (int64_t)tile * S->tile;
+      const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
+      double acc[kNP];
+      float accf[2] = {0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
+      run_pass<CT>(S, sd, phase, k0, k1, acc, accf);
+      write_partial(S->partials[par ^ 1], f32_slots(S->mixed, phase), tile, acc, accf);
+    }
+    if (threadIdx.x == 0) sd.pending = 1;
+    par ^= 1;
+    if (nwg > 1) {
+      __threadfence();  // publish this workgroup's vector and slot stores
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        atomicAdd(&q->counter, 1u);
+        const uint32_t target = (uint32_t)nwg * round;
         int64_t spins = 0;
-        while (__hip_atomic_load(&q->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
-               gen) {
+        while (__hip_atomic_load(&q->counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+               target) {
           __builtin_amdgcn_s_sleep(1);
           if (++spins > P.spin_limit) {
-            q->status = GPCG_ERR_HANG;
-            __hip_atomic_store(&q->phase, (int32_t)PH_DONE, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            if (q->host_flag)
-              __hip_atomic_store(q->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             s_exit = 1;
             break;
           }
         }
+        __threadfence();
       }
-      __threadfence();
     }
     __syncthreads();
-    if (s_exit) break;
+    if (s_exit) {
+      if (threadIdx.x == 0) {
+        sd.status = GPCG_ERR_HANG;
+        sd.phase = PH_DONE;
+      }
+      __syncthreads();
+      break;
+    }
+  }
+  if (lw == 0) {
+    if (threadIdx.x == 0) sd.pending = 0;
+    __syncthreads();
+    copy_dyn(&sd, &q->dyn[0]);
+    copy_dyn(&sd, &q->dyn[1]);
+    __syncthreads();
+    if (threadIdx.x == 0 && S->host_flag) {
+      __threadfence();
+      __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
 // Building blocks exposed through the C ABI.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void spmv_kernel(const QPState *q, const T *__restrict__ v,
+__global__ __launch_bounds__(kBlock) void spmv_kernel(const QPDev *q, const T *__restrict__ v,
                                                       T *__restrict__ y,
                                                       const uint8_t *__restrict__ mask) {
-  const OpView<T> A = op_view<T>(q);
-  const int64_t n = q->n;
+  const OpView<T> A = op_view<T>(&q->st);
+  const int64_t n = q->st.n;
   auto vv = [&](int64_t j) { return v[j]; };
-  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * kBlock) {
+  for (int64_t k = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * kBlock + threadIdx.x;
+       k < n; k += (int64_t)gridDim.x * kBlock) {
     if (mask && !mask[k]) {
       y[k] = T(0);
       continue;
@@ -790,14 +871,10 @@ void *gpcg_step_kernel_ptr(int mixed) {
   return mixed ? (void *)&step_kernel<float> : (void *)&step_kernel<double>;
 }
 
-void *gpcg_persistent_kernel_ptr(int mixed) {
-  return mixed ? (void *)&persistent_kernel<float> : (void *)&persistent_kernel<double>;
-}
-
 int gpcg_persistent_max_blocks(int mixed, int *blocks_per_cu) {
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, mixed ? (const void *)&persistent_kernel<float>
-                           : (const void *)&persistent_kernel<double>,
+      blocks_per_cu,
+      mixed ? (const void *)&persistent_kernel<float> : (const void *)&persistent_kernel<double>,
       kBlock, 0);
   return e == hipSuccess ? 0 : -1;
 }
@@ -829,9 +906,9 @@ static int grid_for(int64_t n) {
   return (int)g;
 }
 
-int gpcg_launch_spmv(const QPState *dqp, const QPState &hqp, const void *v, void *y,
-                     const uint8_t *mask, int f32, void *stream) {
-  const int grid = grid_for(hqp.n);
+int gpcg_launch_spmv(const QPDev *dqp, int64_t n, const void *v, void *y, const uint8_t *mask,
+                     int f32, void *stream) {
+  const int grid = grid_for(n);
   if (f32)
     hipLaunchKernelGGL(spmv_kernel<float>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, dqp,
                        (const float *)v, (float *)y, mask);
@@ -841,16 +918,14 @@ int gpcg_launch_spmv(const QPState *dqp, const QPState &hqp, const void *v, void
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int gpcg_launch_pgrad(const QPState *dqp, const QPState &hqp, const double *x, const double *l,
-                      const double *u, const double *g, double *pg, double *out4, void *stream) {
-  (void)dqp;
-  // partial slots live in the handle's partial area, which holds >= 2048 tiles
-  int grid = grid_for(hqp.n);
+int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
+                      const double *g, double *pg, double *part, double *out4, void *stream) {
+  int grid = grid_for(n);
   if (grid > 2048) grid = 2048;
-  hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, hqp.n, x, l,
-                     u, g, pg, hqp.partials);
+  hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x, l, u,
+                     g, pg, part);
   hipLaunchKernelGGL(pgrad_final_kernel, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
-                     hqp.partials, out4);
+                     part, out4);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -1,9 +1,11 @@
 // gpcg_runtime.cpp -- host side of the C ABI declared in include/gpcg.h.
 //
-// The runtime validates descriptors, carves the caller's workspace, fills the
-// device-resident QPState of every solve and then only replays launches of
-// the pass kernel (as chunks of a HIP graph) until the device raises the DONE
-// flag in mapped host memory.  All GPCG decisions are taken on the device.
+// The runtime validates descriptors, carves the caller's workspace, writes the
+// device-resident state of each solve (QPDev) and then only replays launches
+// of the pass kernel -- as chunks of a HIP graph -- until the device raises
+// the DONE flag in mapped host memory.  Every GPCG decision is taken on the
+// device.  Launch i reads state and partial sums of parity i & 1 and writes
+// the other parity; chunks hold an even number of launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,7 +19,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/gpcg.h"
+#include "gpcg.h"
 #include "gpcg_internal.h"
 
 using namespace gpcg;
@@ -90,33 +92,34 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "unknown free-set mode");
   if (o->tile < 0 || o->tile % kBlock != 0 || o->tile > (1 << 16))
     return fail(GPCG_ERR_ARG, "tile must be a multiple of 256 in [256, 65536]");
-  if (o->chunk < 0 || o->chunk > 4096) return fail(GPCG_ERR_ARG, "chunk out of range");
+  if (o->chunk < 0 || o->chunk > 4096 || (o->chunk & 1))
+    return fail(GPCG_ERR_ARG, "chunk must be even and at most 4096");
   if (o->max_stall < 1) return fail(GPCG_ERR_ARG, "max_stall must be >= 1");
   return GPCG_OK;
 }
 
 // Unknowns per workgroup and pass, chosen from the size alone so that a QP
 // reduces in the same order whether it is solved alone or inside a batch.
-// Small grids use many small tiles (latency: more workgroups in flight);
-// large grids use larger tiles (fewer partial slots, longer streams per
-// workgroup).  Tuned on MI355X; overridable with gpcg_options.tile.
+// One unknown per thread while that keeps at most 1024 tiles (every
+// workgroup sums all tile slots of the previous pass), then more.
 int tuned_tile(int64_t n) {
-  if (n <= (int64_t)1 << 17) return 256;
-  if (n <= (int64_t)1 << 20) return 512;
-  return 1024;
+  const int64_t per = ((int64_t)1024 * kBlock);
+  const int64_t e = (n + per - 1) / per;
+  return (int)(kBlock * std::max<int64_t>(1, e));
 }
 
 struct Layout {
-  size_t state, partials, g, w, r, p0, p1, mask, wx32, wy32, vals32, scratch, total;
+  size_t qp, part0, part1, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
+  size_t wx32, wy32, vals32, total;
   int tile, ntiles;
 };
 
-Layout layout_for(const gpcg_operator *op, const gpcg_options *o) {
+Layout layout_for(const gpcg_operator *op, int precision, int tile_opt) {
   Layout L{};
   const int64_t n = op_n(op);
-  const bool mixed = o->precision == GPCG_PREC_MIXED;
+  const bool mixed = precision == GPCG_PREC_MIXED;
   const size_t ct = mixed ? 4 : 8;
-  L.tile = o->tile > 0 ? o->tile : tuned_tile(n);
+  L.tile = tile_opt > 0 ? tile_opt : tuned_tile(n);
   L.ntiles = (int)((n + L.tile - 1) / L.tile);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -124,14 +127,21 @@ Layout layout_for(const gpcg_operator *op, const gpcg_options *o) {
     off += align_up(bytes);
     return at;
   };
-  L.state = take(sizeof(QPState));
-  L.partials = take(sizeof(double) * kNP * (size_t)std::max(L.ntiles, 2048));
-  L.scratch = take(sizeof(double) * 8);
-  L.g = take(8 * (size_t)n);
+  L.qp = take(sizeof(QPDev));
+  L.part0 = take(sizeof(double) * kNP * (size_t)L.ntiles);
+  L.part1 = take(sizeof(double) * kNP * (size_t)L.ntiles);
+  L.pgpart = take(sizeof(double) * 4 * 2048 + 64);
+  L.x1 = take(8 * (size_t)n);
+  L.g0 = take(8 * (size_t)n);
+  L.g1 = take(8 * (size_t)n);
+  L.rho0 = take(ct * (size_t)n);
+  L.rho1 = take(ct * (size_t)n);
+  L.uq0 = take(ct * (size_t)n);
+  L.uq1 = take(ct * (size_t)n);
+  L.sq0 = take(ct * (size_t)n);
+  L.sq1 = take(ct * (size_t)n);
+  L.p = take(ct * (size_t)n);
   L.w = take(ct * (size_t)n);
-  L.r = take(ct * (size_t)n);
-  L.p0 = take(ct * (size_t)n);
-  L.p1 = take(ct * (size_t)n);
   L.mask = take((size_t)n);
   L.wx32 = L.wy32 = L.vals32 = 0;
   if (mixed && op->kind == GPCG_OP_STENCIL5_VAR) {
@@ -151,130 +161,9 @@ void magic_for(int32_t d, uint64_t *magic, int32_t *shift) {
 }
 
 struct PinnedWords {
-  int32_t *host = nullptr;   // mapped, coherent host memory
-  int32_t *dev = nullptr;    // its device address
+  int32_t *host = nullptr;  // mapped, coherent host memory
+  int32_t *dev = nullptr;   // its device address
 };
-
-}  // namespace
-
-// ------------------------------------------------------------------ handle
-
-struct gpcg_handle_s {
-  gpcg_operator op;
-  gpcg_options opt;
-  hipStream_t stream;
-  char *ws;
-  size_t ws_bytes;
-  Layout L;
-  QPState tmpl;         // static part, filled at create
-  QPState *dqp;         // device state
-  QPState *stage;       // pinned host staging for uploads / downloads
-  PinnedWords flag;     // DONE flag written by the device
-  // single-QP launch tables (device): pointer array + prefix
-  QPState **dqptrs;
-  int32_t *dprefix;
-  hipGraphExec_t graph = nullptr;
-  int graph_chunk = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  double tick_hz;
-};
-
-namespace {
-
-// Algorithmic HBM bytes of one pass (each array touched once; stencil
-// neighbours assumed reused on chip).  `rows` is the unknowns a pass sweeps
-// with full traffic: n for passes over all unknowns, m (the free count) for
-// CG and projected-search passes, which skip the active set after reading
-// its mask byte.
-struct PassBytes {
-  double per_var[PH_COUNT];   // bytes per unknown, every unknown
-  double per_free[PH_COUNT];  // extra bytes per free unknown (masked passes)
-};
-
-PassBytes pass_bytes(const QPState &q) {
-  PassBytes B{};
-  const bool mixed = q.mixed != 0;
-  const double c = mixed ? 4.0 : 8.0;  // CG vector element
-  double coef64 = 0.0, coefc = 0.0;    // operator bytes per row
-  if (q.op_kind == OPK_VAR) {
-    coef64 = 16.0;
-    coefc = mixed ? 8.0 : 16.0;
-  } else if (q.op_kind == OPK_CSR) {
-    // rowptr + (colind + value) per stored entry; ~5 entries per row
-    const double nnz_row = q.n > 0 ? 5.0 : 0.0;
-    coef64 = 4.0 + nnz_row * 12.0;
-    coefc = 4.0 + nnz_row * (mixed ? 8.0 : 12.0);
-  }
-  B.per_var[PH_PROJECT] = 40;                  // x, l, u, b in; x out
-  B.per_var[PH_GRAD] = 40 + coef64;            // x, l, u, b in; g out
-  B.per_var[PH_GP_ALPHA] = 32 + coef64;        // x, l, u, g
-  B.per_var[PH_GP_TRIAL] = 32 + coef64;        // x, l, u, g
-  B.per_var[PH_GP_ACCEPT] = 40;                // x, l, u, g in; x out
-  B.per_var[PH_CG_INIT] = 32 + 1 + 2 * c;      // x, l, u, g in; mask, r, w out
-  B.per_var[PH_CG_A] = 1;                      // mask
-  B.per_free[PH_CG_A] = 3 * c + coefc;         // r, p_old in; p out
-  B.per_var[PH_CG_B] = 1;
-  B.per_free[PH_CG_B] = 5 * c + coefc;         // p, w, r in; w, r out
-  B.per_var[PH_PS_TRIAL] = 1;
-  B.per_free[PH_PS_TRIAL] = 32 + c + coef64;   // x, l, u, g, w
-  B.per_var[PH_PS_ACCEPT] = 1;
-  B.per_free[PH_PS_ACCEPT] = 32 + c;           // x, l, u, w in; x out
-  return B;
-}
-
-double solve_bytes(const QPState &q) {
-  PassBytes B = pass_bytes(q);
-  double total = 0.0;
-  for (int p = 0; p < PH_DONE; ++p) total += B.per_var[p] * (double)q.pass_count[p] * (double)q.n;
-  // free-row traffic: cg_free_rows sums m over CG_A, CG_B, PS_TRIAL, PS_ACCEPT
-  const int64_t nA = q.pass_count[PH_CG_A], nB = q.pass_count[PH_CG_B];
-  const int64_t nT = q.pass_count[PH_PS_TRIAL], nS = q.pass_count[PH_PS_ACCEPT];
-  const int64_t cnt = nA + nB + nT + nS;
-  if (cnt > 0) {
-    const double mean_m = (double)q.cg_free_rows / (double)cnt;
-    total += mean_m * (B.per_free[PH_CG_A] * nA + B.per_free[PH_CG_B] * nB +
-                       B.per_free[PH_PS_TRIAL] * nT + B.per_free[PH_PS_ACCEPT] * nS);
-  }
-  return total;
-}
-
-void fill_stats(const QPState &q, double tick_hz, gpcg_stats *st) {
-  if (!st) return;
-  std::memset(st, 0, sizeof(*st));
-  st->status = q.status;
-  st->outer_iters = q.outer_iters;
-  st->gp_iters = q.gp_iters;
-  st->cg_iters = q.cg_iters;
-  st->backtracks = q.backtracks;
-  st->face_repeats = q.face_repeats;
-  st->cg_phases = q.cg_phases;
-  st->x0_projected = q.x0_projected;
-  st->pg0 = q.pg0;
-  st->pg = q.pgn;
-  st->tau = q.tau;
-  st->q = q.q;
-  st->n_lower = q.n_lower;
-  st->n_upper = q.n_upper;
-  st->n_free = q.n - q.n_lower - q.n_upper;
-  st->passes = q.passes;
-  st->bytes = solve_bytes(q);
-  const double ms = 1e3 / tick_hz;
-  st->ms_cg = q.t_bucket[TB_CG] * ms;
-  st->ms_gp = q.t_bucket[TB_GP] * ms;
-  st->ms_search = q.t_bucket[TB_SEARCH] * ms;
-  st->ms_other = q.t_bucket[TB_OTHER] * ms;
-}
-
-// Resets the dynamic part of a state for a new solve.
-void reset_dynamic(QPState &q) {
-  const size_t off = offsetof(QPState, ticket);
-  std::memset(reinterpret_cast<char *>(&q) + off, 0, sizeof(QPState) - off);
-  q.phase = PH_PROJECT;
-  q.ctx = CTX_INIT;
-  q.status = GPCG_OK;
-  q.gp_decmax = -INFINITY;
-  q.cg_decmax = -INFINITY;
-}
 
 int alloc_flag(PinnedWords *f, size_t words) {
   void *h = nullptr;
@@ -295,21 +184,103 @@ double wall_clock_hz() {
   return khz * 1e3;
 }
 
-// Builds a graph of `count` chained launches of the pass kernel.
+// Options copied into the static state.
+void put_options(QPStatic &s, const gpcg_options &o) {
+  s.tol_rel = o.tol_rel;
+  s.tol_abs = o.tol_abs;
+  s.eta1 = o.eta1;
+  s.eta2 = o.eta2;
+  s.eta2_reduce = o.eta2_reduce;
+  s.mu = o.mu;
+  s.max_outer = o.max_outer;
+  s.max_gp = o.max_gp;
+  s.max_backtrack = o.max_backtrack;
+  s.max_cg = o.max_cg;
+  s.max_stall = o.max_stall;
+}
+
+// The initial state of a solve (phase INIT, nothing pending).
+void initial_dyn(QPDyn &d) {
+  std::memset(&d, 0, sizeof(d));
+  d.phase = PH_INIT;
+  d.ctx = CTX_INIT;
+  d.status = GPCG_OK;
+  d.gp_decmax = -INFINITY;
+  d.cg_decmax = -INFINITY;
+}
+
+// Algorithmic HBM bytes of a finished solve: every array a pass touches is
+// counted once per pass (stencil neighbours are assumed reused on chip).
+// Passes that sweep only the free set (CG iterations) count the mask byte for
+// every unknown and the vector traffic for the free unknowns.
+double solve_bytes(const QPStatic &s, const QPDyn &d) {
+  const bool mixed = s.mixed != 0;
+  const double c = mixed ? 4.0 : 8.0;
+  double coef64 = 0.0, coefc = 0.0;
+  if (s.op_kind == OPK_VAR) {
+    coef64 = 16.0;
+    coefc = mixed ? 8.0 : 16.0;
+  } else if (s.op_kind == OPK_CSR) {
+    coef64 = 4.0 + 5.0 * 12.0;  // rowptr + ~5 (colind, value) per row
+    coefc = 4.0 + 5.0 * (mixed ? 8.0 : 12.0);
+  }
+  const double n = (double)s.n;
+  const double it = (double)d.pass_count[PH_CG_ITER];
+  const double mean_m = it > 0 ? (double)d.cg_free_rows / it : 0.5 * n;
+  double B = 0.0;
+  B += d.pass_count[PH_INIT] * n * (48.0 + coef64);      // x0, l, u, b in; x, g out
+  B += d.pass_count[PH_GP_ALPHA] * n * (32.0 + coef64);  // x, l, u, g
+  B += d.pass_count[PH_GP_TRIAL] * n * (56.0 + coef64);  // x, l, u, g, b in; x', g' out
+  B += d.pass_count[PH_CG_INIT] * (n * 33.0 + mean_m * (3 * c + coefc) + (n - mean_m) * 7 * c);
+  B += (double)d.cg_free_rows * (10 * c + coefc) + it * n * 1.0;  // rho,u,s,p,w in+out; mask
+  B += d.pass_count[PH_PS_TRIAL] * (n * (57.0 + coef64) + mean_m * c);
+  return B;
+}
+
+void fill_stats(const QPStatic &s, const QPDyn &d, double tick_hz, gpcg_stats *st) {
+  if (!st) return;
+  std::memset(st, 0, sizeof(*st));
+  st->status = d.status;
+  st->outer_iters = d.outer_iters;
+  st->gp_iters = d.gp_iters;
+  st->cg_iters = d.cg_iters;
+  st->backtracks = d.backtracks;
+  st->face_repeats = d.face_repeats;
+  st->cg_phases = d.cg_phases;
+  st->x0_projected = d.x0_projected;
+  st->pg0 = d.pg0;
+  st->pg = d.pgn;
+  st->tau = d.tau;
+  st->q = d.q;
+  st->n_lower = d.n_lower;
+  st->n_upper = d.n_upper;
+  st->n_free = s.n - d.n_lower - d.n_upper;
+  st->passes = d.passes;
+  st->bytes = solve_bytes(s, d);
+  const double ms = 1e3 / tick_hz;
+  st->ms_cg = d.t_bucket[TB_CG] * ms;
+  st->ms_gp = d.t_bucket[TB_GP] * ms;
+  st->ms_search = d.t_bucket[TB_SEARCH] * ms;
+  st->ms_other = d.t_bucket[TB_OTHER] * ms;
+}
+
+// A graph of `count` chained launches of the pass kernel with alternating
+// parity (count is even, so replays continue the parity sequence).
 int build_chain_graph(const StepLaunch &L, int mixed, int count, hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   HIP_OK(hipGraphCreate(&g, 0));
-  hipKernelNodeParams p{};
-  p.func = gpcg_step_kernel_ptr(mixed);
-  p.gridDim = dim3((unsigned)L.total_tiles);
-  p.blockDim = dim3(kBlock);
-  p.sharedMemBytes = 0;
-  StepLaunch arg = L;
-  void *args[] = {&arg};
-  p.kernelParams = args;
-  p.extra = nullptr;
   hipGraphNode_t prev = nullptr;
   for (int i = 0; i < count; ++i) {
+    hipKernelNodeParams p{};
+    p.func = gpcg_step_kernel_ptr(mixed);
+    p.gridDim = dim3((unsigned)L.total_tiles);
+    p.blockDim = dim3(kBlock);
+    p.sharedMemBytes = 0;
+    StepLaunch arg = L;
+    arg.parity = i & 1;
+    void *args[] = {&arg};
+    p.kernelParams = args;
+    p.extra = nullptr;
     hipGraphNode_t node;
     hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
     if (e != hipSuccess) {
@@ -325,40 +296,41 @@ int build_chain_graph(const StepLaunch &L, int mixed, int count, hipGraphExec_t 
   return GPCG_OK;
 }
 
-// Replays chunks of `chunk` passes until every flag in `flags` is set.
-// Keeps one chunk queued behind the one the host waits on, so the GPU never
-// idles while the host checks.  Returns launches issued via *launches.
-int run_until_done(hipStream_t stream, const StepLaunch &L, int mixed, int chunk,
-                   hipGraphExec_t graph, hipEvent_t *ev, volatile int32_t *flags, int nflags,
-                   int64_t max_launches, int64_t *launches, int64_t *checks) {
-  auto all_done = [&]() {
-    for (int i = 0; i < nflags; ++i)
-      if (!flags[i]) return false;
-    return true;
-  };
-  auto launch_chunk = [&]() -> int {
-    if (graph) {
-      HIP_OK(hipGraphLaunch(graph, stream));
-    } else {
-      for (int i = 0; i < chunk; ++i)
-        if (gpcg_launch_step(L, mixed, stream) != 0)
-          return fail(GPCG_ERR_HIP, "pass kernel launch failed");
-    }
-    *launches += chunk;
+// Launches one chunk: the graph, or `chunk` plain launches of alternating
+// parity starting at 0.
+int launch_chunk(hipStream_t stream, StepLaunch L, int mixed, int chunk, hipGraphExec_t graph) {
+  if (graph) {
+    HIP_OK(hipGraphLaunch(graph, stream));
     return GPCG_OK;
-  };
-  int rc = launch_chunk();
+  }
+  for (int i = 0; i < chunk; ++i) {
+    L.parity = i & 1;
+    if (gpcg_launch_step(L, mixed, stream) != 0)
+      return fail(GPCG_ERR_HIP, "pass kernel launch failed");
+  }
+  return GPCG_OK;
+}
+
+// Replays chunks until `done()` holds.  Keeps one chunk queued behind the one
+// the host waits on, so the GPU does not idle while the host checks.
+template <class Done>
+int run_until(hipStream_t stream, const StepLaunch &L, int mixed, int chunk, hipGraphExec_t graph,
+              hipEvent_t *ev, Done done, int64_t max_launches, int64_t *launches,
+              int64_t *checks) {
+  int rc = launch_chunk(stream, L, mixed, chunk, graph);
   if (rc) return rc;
+  *launches += chunk;
   HIP_OK(hipEventRecord(ev[0], stream));
   for (int64_t i = 1;; ++i) {
     if (*launches >= max_launches)
       return fail(GPCG_ERR_HANG, "device did not finish within the launch budget");
-    rc = launch_chunk();
+    rc = launch_chunk(stream, L, mixed, chunk, graph);
     if (rc) return rc;
+    *launches += chunk;
     HIP_OK(hipEventRecord(ev[i & 1], stream));
     hipEvent_t prev = ev[(i - 1) & 1];
     for (;;) {
-      if (all_done()) break;
+      if (done()) break;
       hipError_t e = hipEventQuery(prev);
       if (e == hipSuccess) break;
       if (e != hipErrorNotReady)
@@ -366,7 +338,7 @@ int run_until_done(hipStream_t stream, const StepLaunch &L, int mixed, int chunk
       std::this_thread::yield();
     }
     *checks += 1;
-    if (all_done()) break;
+    if (done()) break;
   }
   HIP_OK(hipStreamSynchronize(stream));
   return GPCG_OK;
@@ -374,8 +346,31 @@ int run_until_done(hipStream_t stream, const StepLaunch &L, int mixed, int chunk
 
 int default_chunk(const gpcg_options &o) { return o.chunk > 0 ? o.chunk : 32; }
 
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+
+struct gpcg_handle_s {
+  gpcg_operator op;
+  gpcg_options opt;
+  hipStream_t stream;
+  char *ws;
+  size_t ws_bytes;
+  Layout L;
+  QPStatic st;          // static part (x[0] filled per solve)
+  QPDev *dqp;           // device state
+  QPDev *stage;         // pinned host staging for uploads / downloads
+  PinnedWords flag;     // DONE flag written by the device
+  hipGraphExec_t graph = nullptr;
+  int graph_chunk = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double tick_hz;
+};
+
+namespace {
+
 void fill_static(gpcg_handle_s *h) {
-  QPState &q = h->tmpl;
+  QPStatic &q = h->st;
   std::memset(&q, 0, sizeof(q));
   const gpcg_operator &op = h->op;
   char *ws = h->ws;
@@ -401,25 +396,54 @@ void fill_static(gpcg_handle_s *h) {
   q.colind = op.colind;
   q.vals = op.vals;
   q.vals32 = L.vals32 ? (const float *)(ws + L.vals32) : nullptr;
-  q.g = (double *)(ws + L.g);
-  q.vw = ws + L.w;
-  q.vr = ws + L.r;
-  q.vp0 = ws + L.p0;
-  q.vp1 = ws + L.p1;
+  q.x[1] = (double *)(ws + L.x1);
+  q.g[0] = (double *)(ws + L.g0);
+  q.g[1] = (double *)(ws + L.g1);
+  q.rho[0] = ws + L.rho0;
+  q.rho[1] = ws + L.rho1;
+  q.uq[0] = ws + L.uq0;
+  q.uq[1] = ws + L.uq1;
+  q.sq[0] = ws + L.sq0;
+  q.sq[1] = ws + L.sq1;
+  q.pv = ws + L.p;
+  q.wv = ws + L.w;
   q.mask = (uint8_t *)(ws + L.mask);
-  q.partials = (double *)(ws + L.partials);
+  q.partials[0] = (double *)(ws + L.part0);
+  q.partials[1] = (double *)(ws + L.part1);
   q.host_flag = h->flag.dev;
-  q.tol_rel = h->opt.tol_rel;
-  q.tol_abs = h->opt.tol_abs;
-  q.eta1 = h->opt.eta1;
-  q.eta2 = h->opt.eta2;
-  q.eta2_reduce = h->opt.eta2_reduce;
-  q.mu = h->opt.mu;
-  q.max_outer = h->opt.max_outer;
-  q.max_gp = h->opt.max_gp;
-  q.max_backtrack = h->opt.max_backtrack;
-  q.max_cg = h->opt.max_cg;
-  q.max_stall = h->opt.max_stall;
+  put_options(q, h->opt);
+}
+
+// Uploads the state of a new solve of handle h (not yet started).
+int upload_solve(gpcg_handle_s *h, const double *b, const double *l, const double *u, double *x,
+                 int32_t *flag_dev, hipStream_t stream) {
+  QPDev &q = *h->stage;
+  std::memset(&q, 0, sizeof(q));
+  q.st = h->st;
+  q.st.b = b;
+  q.st.l = l;
+  q.st.u = u;
+  q.st.x[0] = x;
+  q.st.host_flag = flag_dev;
+  initial_dyn(q.dyn[0]);
+  initial_dyn(q.dyn[1]);
+  HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPDev), hipMemcpyHostToDevice, stream));
+  return GPCG_OK;
+}
+
+// After the solve: the answer into the caller's x when it sits in the spare
+// copy, the gradient into g_out; the final state into the staging copy.
+int finish_solve(gpcg_handle_s *h, int final_parity, double *g_out, hipStream_t stream) {
+  HIP_OK(hipMemcpyAsync(h->stage, h->dqp, sizeof(QPDev), hipMemcpyDeviceToHost, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  const QPDyn &d = h->stage->dyn[final_parity];
+  const QPStatic &s = h->stage->st;
+  const size_t bytes = sizeof(double) * (size_t)s.n;
+  if (d.cur == 1)
+    HIP_OK(hipMemcpyAsync(s.x[0], s.x[1], bytes, hipMemcpyDeviceToDevice, stream));
+  if (g_out) HIP_OK(hipMemcpyAsync(g_out, s.g[d.cur], bytes, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  return GPCG_OK;
 }
 
 }  // namespace
@@ -457,7 +481,7 @@ int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
-  *bytes = layout_for(op, &o).total;
+  *bytes = layout_for(op, o.precision, o.tile).total;
   return GPCG_OK;
 }
 
@@ -472,7 +496,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
-  Layout L = layout_for(op, &o);
+  Layout L = layout_for(op, o.precision, o.tile);
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
     return fail(GPCG_ERR_WORKSPACE, "workspace missing or not 256-byte aligned");
   if (ws_bytes < L.total)
@@ -484,7 +508,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;
   h->L = L;
-  h->dqp = (QPState *)(h->ws + L.state);
+  h->dqp = (QPDev *)(h->ws + L.qp);
   h->tick_hz = wall_clock_hz();
   auto cleanup = [&](int code) {
     gpcg_destroy(h);
@@ -493,28 +517,13 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   rc = alloc_flag(&h->flag, 16);
   if (rc) return cleanup(rc);
   void *st = nullptr;
-  if (hipHostMalloc(&st, sizeof(QPState) + 2 * sizeof(void *) + 64, hipHostMallocDefault) !=
-      hipSuccess)
+  if (hipHostMalloc(&st, sizeof(QPDev), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "hipHostMalloc of the staging state failed"));
-  h->stage = (QPState *)st;
-  // single-QP launch tables live in the scratch slot of the workspace
-  h->dqptrs = (QPState **)(h->ws + L.scratch);
-  h->dprefix = (int32_t *)(h->ws + L.scratch + 2 * sizeof(void *));
+  h->stage = (QPDev *)st;
   fill_static(h);
   if (hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "hipEventCreate failed"));
-  // the launch tables: {dqp} and {0, ntiles}
-  struct {
-    QPState *p[2];
-    int32_t pre[4];
-  } tables{};
-  tables.p[0] = h->dqp;
-  tables.pre[0] = 0;
-  tables.pre[1] = L.ntiles;
-  if (hipMemcpyAsync(h->ws + L.scratch, &tables, sizeof(tables), hipMemcpyHostToDevice,
-                     h->stream) != hipSuccess)
-    return cleanup(fail(GPCG_ERR_HIP, "upload of the launch tables failed"));
   // FP32 copy of the operator for the mixed form
   if (L.wx32) {
     if (gpcg_launch_convert_f32(op->wx, (float *)(h->ws + L.wx32),
@@ -549,65 +558,59 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   if (!b || !l || !u || !x) return fail(GPCG_ERR_ARG, "b, l, u and x are required");
   const double t0 = now_s();
   HIP_OK(hipStreamSynchronize(h->stream));  // the staging buffer may still be in flight
-  QPState &q = *h->stage;
-  q = h->tmpl;
-  q.b = b;
-  q.l = l;
-  q.u = u;
-  q.x = x;
-  reset_dynamic(q);
   h->flag.host[0] = 0;
-  HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPState), hipMemcpyHostToDevice, h->stream));
-  StepLaunch SL{h->dqptrs, h->dprefix, 1, h->L.ntiles};
+  int rc = upload_solve(h, b, l, u, x, h->flag.dev, h->stream);
+  if (rc) return rc;
+  StepLaunch SL{};
+  SL.single = h->dqp;
+  SL.nqp = 1;
+  SL.total_tiles = h->L.ntiles;
   const int chunk = default_chunk(h->opt);
   if (h->opt.use_graph && (!h->graph || h->graph_chunk != chunk)) {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
-    int rc = build_chain_graph(SL, h->tmpl.mixed, chunk, &h->graph);
+    rc = build_chain_graph(SL, h->st.mixed, chunk, &h->graph);
     if (rc) return rc;
     h->graph_chunk = chunk;
   }
   int64_t launches = 0, checks = 0;
-  int rc = run_until_done(h->stream, SL, h->tmpl.mixed, chunk,
-                          h->opt.use_graph ? h->graph : nullptr, h->ev, h->flag.host, 1,
-                          (int64_t)1 << 26, &launches, &checks);
+  volatile int32_t *flag = h->flag.host;
+  rc = run_until(h->stream, SL, h->st.mixed, chunk, h->opt.use_graph ? h->graph : nullptr, h->ev,
+                 [&] { return *flag != 0; }, (int64_t)1 << 26, &launches, &checks);
   if (rc) return rc;
-  HIP_OK(hipMemcpyAsync(h->stage, h->dqp, sizeof(QPState), hipMemcpyDeviceToHost, h->stream));
-  if (g_out)
-    HIP_OK(hipMemcpyAsync(g_out, h->tmpl.g, sizeof(double) * (size_t)h->tmpl.n,
-                          hipMemcpyDeviceToDevice, h->stream));
-  HIP_OK(hipStreamSynchronize(h->stream));
-  const QPState &res = *h->stage;
+  rc = finish_solve(h, (int)(launches & 1), g_out, h->stream);
+  if (rc) return rc;
+  const QPDyn &d = h->stage->dyn[launches & 1];
   if (stats) {
-    fill_stats(res, h->tick_hz, stats);
+    fill_stats(h->stage->st, d, h->tick_hz, stats);
     stats->launches = launches;
     stats->host_checks = checks;
     stats->ms_total = (now_s() - t0) * 1e3;
   }
-  if (res.status < 0) g_last_error = gpcg_status_string(res.status);
-  return res.status;
+  if (d.status < 0) g_last_error = gpcg_status_string(d.status);
+  return d.status;
 }
 
 int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
   // the kernel reads the operator from the device state: refresh it
-  QPState &q = *h->stage;
   HIP_OK(hipStreamSynchronize(h->stream));
-  q = h->tmpl;
-  HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPState), hipMemcpyHostToDevice, h->stream));
-  if (gpcg_launch_spmv(h->dqp, h->tmpl, v, y, mask, 0, h->stream))
+  h->stage->st = h->st;
+  HIP_OK(hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
+                        h->stream));
+  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 0, h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
 }
 
 int gpcg_spmv_f32(gpcg_handle h, const float *v, float *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
-  if (!h->tmpl.mixed) return fail(GPCG_ERR_ARG, "handle was not created with GPCG_PREC_MIXED");
-  QPState &q = *h->stage;
+  if (!h->st.mixed) return fail(GPCG_ERR_ARG, "handle was not created with GPCG_PREC_MIXED");
   HIP_OK(hipStreamSynchronize(h->stream));
-  q = h->tmpl;
-  HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPState), hipMemcpyHostToDevice, h->stream));
-  if (gpcg_launch_spmv(h->dqp, h->tmpl, v, y, mask, 1, h->stream))
+  h->stage->st = h->st;
+  HIP_OK(hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
+                        h->stream));
+  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 1, h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
 }
@@ -616,8 +619,9 @@ int gpcg_projected_gradient(gpcg_handle h, const double *x, const double *l, con
                             const double *g, double *pg, double *norm2, int64_t *n_lower,
                             int64_t *n_upper, int64_t *n_nonbinding) {
   if (!h || !x || !l || !u || !g) return fail(GPCG_ERR_ARG, "handle, x, l, u, g required");
-  double *out4 = (double *)(h->ws + h->L.scratch + 64);
-  if (gpcg_launch_pgrad(h->dqp, h->tmpl, x, l, u, g, pg, out4, h->stream))
+  double *part = (double *)(h->ws + h->L.pgpart);
+  double *out4 = part + 4 * 2048;
+  if (gpcg_launch_pgrad(h->st.n, x, l, u, g, pg, part, out4, h->stream))
     return fail(GPCG_ERR_HIP, "projected-gradient launch failed");
   double r[4];
   HIP_OK(hipMemcpyAsync(r, out4, sizeof(r), hipMemcpyDeviceToHost, h->stream));
@@ -649,7 +653,7 @@ const char *gpcg_status_string(int s) {
 const char *gpcg_last_error(void) { return g_last_error.c_str(); }
 
 const char *gpcg_build_info(void) {
-  return "gpcg-mi355x 0.1 (HIP, offload gfx950, wave64, FP64 + mixed FP32 reduced CG)";
+  return "gpcg-mi355x 0.2 (HIP, offload gfx950, wave64, FP64 + mixed FP32 reduced CG)";
 }
 
 }  // extern "C"
@@ -658,23 +662,15 @@ const char *gpcg_build_info(void) {
 
 namespace {
 
-// Launch tables for a set of QPs: pointer array + tile prefix (stepped form)
-// or workgroup-slot prefix (persistent form).  Lives at the start of a
-// workspace; `stage` is pinned host memory of the same layout.
-struct Tables {
-  QPState **qptrs;   // device
-  int32_t *prefix;   // device
-  size_t bytes;
-};
-
 size_t tables_bytes(int count) {
   return align_up(sizeof(void *) * (size_t)count) + align_up(sizeof(int32_t) * (count + 1));
 }
 
 // Workgroup slots per QP for the persistent form: proportional to the QP's
-// share of all unknowns, at least one, at most its tile count; the total
-// fits the number of co-resident workgroups.
-std::vector<int32_t> persistent_slots(const std::vector<const QPState *> &qs, int capacity) {
+// share of all unknowns, at least one, at most eight (the per-QP barrier stays
+// cheap) and at most its tile count; the total fits the co-resident
+// workgroups.
+std::vector<int32_t> persistent_slots(const std::vector<const QPStatic *> &qs, int capacity) {
   const int cnt = (int)qs.size();
   std::vector<int32_t> w(cnt, 1);
   if (cnt == 0 || capacity < cnt) return {};
@@ -683,11 +679,11 @@ std::vector<int32_t> persistent_slots(const std::vector<const QPState *> &qs, in
   int used = 0;
   for (int i = 0; i < cnt; ++i) {
     int want = (int)std::floor(capacity * (double)qs[i]->n / total);
-    want = std::max(1, std::min(want, qs[i]->ntiles));
+    want = std::max(1, std::min({want, qs[i]->ntiles, 8}));
     w[i] = want;
     used += want;
   }
-  while (used > capacity) {  // rounding overflow: trim the largest shares
+  while (used > capacity) {
     int arg = (int)(std::max_element(w.begin(), w.end()) - w.begin());
     if (w[arg] <= 1) break;
     --w[arg];
@@ -714,9 +710,11 @@ struct gpcg_batch_s {
   hipStream_t stream;
   char *ws;
   size_t ws_bytes;
-  Tables T;
-  char *stage;          // pinned copy of the tables
-  PinnedWords flags;    // one DONE word per QP
+  QPDev **qptrs;       // device
+  int32_t *prefix;     // device
+  size_t tbytes;
+  char *stage;         // pinned copy of the tables
+  PinnedWords flags;   // one DONE word per QP
   hipEvent_t ev[2] = {nullptr, nullptr};
   int mixed;
 };
@@ -737,7 +735,7 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
     return fail(GPCG_ERR_WORKSPACE, "batch workspace missing, misaligned or too small");
   for (int i = 0; i < count; ++i) {
     if (!handles[i]) return fail(GPCG_ERR_ARG, "NULL handle in batch");
-    if (handles[i]->tmpl.mixed != handles[0]->tmpl.mixed)
+    if (handles[i]->st.mixed != handles[0]->st.mixed)
       return fail(GPCG_ERR_ARG, "all handles of a batch must share the precision");
   }
   auto *b = new gpcg_batch_s();
@@ -745,17 +743,17 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->stream = (hipStream_t)stream;
   b->ws = (char *)workspace;
   b->ws_bytes = ws_bytes;
-  b->T.qptrs = (QPState **)b->ws;
-  b->T.prefix = (int32_t *)(b->ws + align_up(sizeof(void *) * (size_t)count));
-  b->T.bytes = tables_bytes(count);
-  b->mixed = handles[0]->tmpl.mixed;
+  b->qptrs = (QPDev **)b->ws;
+  b->prefix = (int32_t *)(b->ws + align_up(sizeof(void *) * (size_t)count));
+  b->tbytes = tables_bytes(count);
+  b->mixed = handles[0]->st.mixed;
   int rc = alloc_flag(&b->flags, (size_t)count);
   if (rc) {
     delete b;
     return rc;
   }
   void *st = nullptr;
-  if (hipHostMalloc(&st, b->T.bytes, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&st, b->tbytes, hipHostMallocDefault) != hipSuccess) {
     gpcg_batch_destroy(b);
     return fail(GPCG_ERR_HIP, "hipHostMalloc of batch tables failed");
   }
@@ -791,28 +789,20 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     if (!p.b || !p.l || !p.u || !p.x) return fail(GPCG_ERR_ARG, "problem arrays missing");
     gpcg_handle h = b->hs[i];
     HIP_OK(hipStreamSynchronize(h->stream));
-    QPState &q = *h->stage;
-    q = h->tmpl;
-    q.b = p.b;
-    q.l = p.l;
-    q.u = p.u;
-    q.x = p.x;
-    q.host_flag = b->flags.dev + i;
-    reset_dynamic(q);
     b->flags.host[i] = 0;
-    HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPState), hipMemcpyHostToDevice, b->stream));
+    int rc = upload_solve(h, p.b, p.l, p.u, p.x, b->flags.dev + i, b->stream);
+    if (rc) return rc;
   }
-  // tables over all QPs
-  std::vector<const QPState *> qs(cnt);
-  for (int i = 0; i < cnt; ++i) qs[i] = &b->hs[i]->tmpl;
-  auto **qp = (QPState **)b->stage;
+  auto **qp = (QPDev **)b->stage;
   auto *pre = (int32_t *)(b->stage + align_up(sizeof(void *) * (size_t)cnt));
   int64_t launches = 0, checks = 0;
-  int grid = 0;
+  int final_parity = 0;
   if (mode == GPCG_BATCH_PERSISTENT) {
     int cap = 0;
     int rc = persistent_capacity(b->mixed, &cap);
     if (rc) return rc;
+    std::vector<const QPStatic *> qs(cnt);
+    for (int i = 0; i < cnt; ++i) qs[i] = &b->hs[i]->st;
     std::vector<int32_t> w = persistent_slots(qs, cap);
     if (w.empty()) return fail(GPCG_ERR_ARG, "more QPs than co-resident workgroups");
     pre[0] = 0;
@@ -820,89 +810,65 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       qp[i] = b->hs[i]->dqp;
       pre[i + 1] = pre[i] + w[i];
     }
-    grid = pre[cnt];
-    HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->T.bytes, hipMemcpyHostToDevice, b->stream));
-    PersistLaunch P{b->T.qptrs, b->T.prefix, cnt, grid, (int64_t)1 << 22};
+    const int grid = pre[cnt];
+    HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
+    PersistLaunch P{b->qptrs, b->prefix, cnt, grid, (int64_t)1 << 22};
     if (gpcg_launch_persistent(P, grid, b->mixed, b->stream) != 0)
       return fail(GPCG_ERR_HIP, std::string("cooperative launch failed: ") +
                                     hipGetErrorString(hipGetLastError()));
     launches = 1;
     HIP_OK(hipStreamSynchronize(b->stream));
   } else {
-    // stepped: replay chunks; shrink the launch to the unfinished QPs as
-    // they complete (results do not depend on the launch composition)
+    // stepped: replay chunks; shrink the launch to the unfinished QPs as they
+    // complete (results do not depend on the launch composition)
     std::vector<int> active(cnt);
     for (int i = 0; i < cnt; ++i) active[i] = i;
     const int chunk = default_chunk(b->hs[0]->opt);
     while (!active.empty()) {
-      int total = 0;
       pre[0] = 0;
       for (size_t a = 0; a < active.size(); ++a) {
         qp[a] = b->hs[active[a]]->dqp;
-        pre[a + 1] = pre[a] + b->hs[active[a]]->tmpl.ntiles;
+        pre[a + 1] = pre[a] + b->hs[active[a]]->st.ntiles;
       }
-      total = pre[active.size()];
+      const int total = pre[active.size()];
       HIP_OK(hipStreamSynchronize(b->stream));
-      HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->T.bytes, hipMemcpyHostToDevice, b->stream));
-      StepLaunch SL{b->T.qptrs, b->T.prefix, (int32_t)active.size(), total};
+      HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
+      StepLaunch SL{};
+      SL.qps = b->qptrs;
+      SL.prefix = b->prefix;
+      SL.nqp = (int32_t)active.size();
+      SL.total_tiles = total;
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, chunk, &graph);
       if (rc) return rc;
-      // run until at least a third of the launch's tiles belong to finished QPs
-      const int64_t before = launches;
-      (void)before;
-      bool shrink = false;
-      launches += chunk;
-      HIP_OK(hipGraphLaunch(graph, b->stream));
-      HIP_OK(hipEventRecord(b->ev[0], b->stream));
-      for (int64_t i = 1; !shrink; ++i) {
-        if (launches >= ((int64_t)1 << 26)) {
-          (void)hipGraphExecDestroy(graph);
-          return fail(GPCG_ERR_HANG, "batch did not finish within the launch budget");
-        }
-        HIP_OK(hipGraphLaunch(graph, b->stream));
-        launches += chunk;
-        HIP_OK(hipEventRecord(b->ev[i & 1], b->stream));
-        hipEvent_t prev = b->ev[(i - 1) & 1];
-        for (;;) {
-          hipError_t e = hipEventQuery(prev);
-          if (e == hipSuccess) break;
-          if (e != hipErrorNotReady) {
-            (void)hipGraphExecDestroy(graph);
-            return fail(GPCG_ERR_HIP, "hipEventQuery failed");
-          }
-          std::this_thread::yield();
-        }
-        ++checks;
+      // run until at least a third of this launch's tiles belong to finished QPs
+      auto enough = [&]() {
         int done_tiles = 0;
-        for (size_t a = 0; a < active.size(); ++a)
-          if (b->flags.host[active[a]]) done_tiles += b->hs[active[a]]->tmpl.ntiles;
-        if (3 * done_tiles >= total) shrink = true;
-      }
-      HIP_OK(hipStreamSynchronize(b->stream));
+        for (int i : active)
+          if (b->flags.host[i]) done_tiles += b->hs[i]->st.ntiles;
+        return 3 * done_tiles >= total;
+      };
+      rc = run_until(b->stream, SL, b->mixed, chunk, graph, b->ev, enough, (int64_t)1 << 26,
+                     &launches, &checks);
       (void)hipGraphExecDestroy(graph);
+      if (rc) return rc;
       std::vector<int> still;
       for (int i : active)
         if (!b->flags.host[i]) still.push_back(i);
       active.swap(still);
     }
+    final_parity = (int)(launches & 1);
   }
   int first_err = GPCG_OK;
-  for (int i = 0; i < cnt; ++i) {
-    gpcg_handle h = b->hs[i];
-    HIP_OK(hipMemcpyAsync(h->stage, h->dqp, sizeof(QPState), hipMemcpyDeviceToHost, b->stream));
-    if (probs[i].g_out)
-      HIP_OK(hipMemcpyAsync(probs[i].g_out, h->tmpl.g, sizeof(double) * (size_t)h->tmpl.n,
-                            hipMemcpyDeviceToDevice, b->stream));
-  }
-  HIP_OK(hipStreamSynchronize(b->stream));
   const double ms = (now_s() - t0) * 1e3;
   for (int i = 0; i < cnt; ++i) {
     gpcg_handle h = b->hs[i];
-    const QPState &res = *h->stage;
-    if (res.status < 0 && first_err == GPCG_OK) first_err = res.status;
+    int rc = finish_solve(h, final_parity, probs[i].g_out, b->stream);
+    if (rc) return rc;
+    const QPDyn &d = h->stage->dyn[final_parity];
+    if (d.status < 0 && first_err == GPCG_OK) first_err = d.status;
     if (stats) {
-      fill_stats(res, h->tick_hz, &stats[i]);
+      fill_stats(h->stage->st, d, h->tick_hz, &stats[i]);
       stats[i].launches = launches;
       stats[i].host_checks = checks;
       stats[i].ms_total = ms;
@@ -918,48 +884,32 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
 
 namespace {
 
-// Arena bytes of one request: its QPState, reduction slots, resident copies
-// of b, l, u, the iterate x and gradient g, the CG vectors, the free mask
-// and, for edge-weighted stencils, the weights (plus FP32 copies in the
-// mixed form).
+// Arena bytes of one request: its QPDev, the workspace layout of a handle for
+// its operator, resident copies of b, l, u and the start, and for
+// edge-weighted stencils the weights.
 struct ReqLayout {
-  size_t state, partials, b, l, u, x, g, w, r, p0, p1, mask, wx, wy, wx32, wy32, total;
-  int tile, ntiles;
+  Layout L;
+  size_t b, l, u, x0, wx, wy, total;
 };
 
 ReqLayout req_layout(const gpcg_operator *op, int precision) {
   ReqLayout R{};
+  R.L = layout_for(op, precision, 0);
   const int64_t n = op_n(op);
-  const size_t ct = precision == GPCG_PREC_MIXED ? 4 : 8;
-  R.tile = tuned_tile(n);
-  R.ntiles = (int)((n + R.tile - 1) / R.tile);
-  size_t off = 0;
+  size_t off = R.L.total;
   auto take = [&](size_t bytes) {
     size_t at = off;
     off += align_up(bytes);
     return at;
   };
-  R.state = take(sizeof(QPState));
-  R.partials = take(sizeof(double) * kNP * (size_t)R.ntiles);
   R.b = take(8 * (size_t)n);
   R.l = take(8 * (size_t)n);
   R.u = take(8 * (size_t)n);
-  R.x = take(8 * (size_t)n);
-  R.g = take(8 * (size_t)n);
-  R.w = take(ct * (size_t)n);
-  R.r = take(ct * (size_t)n);
-  R.p0 = take(ct * (size_t)n);
-  R.p1 = take(ct * (size_t)n);
-  R.mask = take((size_t)n);
-  R.wx = R.wy = R.wx32 = R.wy32 = 0;
+  R.x0 = take(8 * (size_t)n);
+  R.wx = R.wy = 0;
   if (op->kind == GPCG_OP_STENCIL5_VAR) {
-    const size_t ex = (size_t)op->ny * (op->nx + 1), ey = (size_t)(op->ny + 1) * op->nx;
-    R.wx = take(8 * ex);
-    R.wy = take(8 * ey);
-    if (precision == GPCG_PREC_MIXED) {
-      R.wx32 = take(4 * ex);
-      R.wy32 = take(4 * ey);
-    }
+    R.wx = take(8 * (size_t)op->ny * (op->nx + 1));
+    R.wy = take(8 * (size_t)(op->ny + 1) * op->nx);
   }
   R.total = off;
   return R;
@@ -986,16 +936,17 @@ struct gpcg_server_s {
   hipStream_t stream;
   char *arena;
   size_t header;        // launch tables at the start of the arena
-  Tables T;
+  QPDev **qptrs;
+  int32_t *prefix;
   char *stage_tables;   // pinned
-  QPState *stage;       // pinned, one per slot
+  QPDev *stage;         // pinned, one per slot
   PinnedWords flags;    // one DONE word per slot
   std::vector<SrvSlot> slots;
   std::deque<SrvPending> queue;
-  std::vector<gpcg_completion> done;
+  std::deque<gpcg_completion> done;
   std::map<size_t, size_t> free_list;  // offset -> bytes, coalesced
-  bool dirty = true;
   int resident = 0;
+  int64_t launches = 0;  // parity of the next launch: launches & 1
   double tick_hz;
   gpcg_options solve_opt;
 
@@ -1036,104 +987,112 @@ int srv_admit(gpcg_server_s *s, int slot_id, const SrvPending &p, size_t off) {
   const gpcg_request &rq = p.req;
   const gpcg_operator &op = rq.op;
   const ReqLayout R = req_layout(&op, s->opt.precision);
+  const Layout &L = R.L;
   char *base = s->arena + off;
   const int64_t n = op_n(&op);
   hipStream_t st = s->stream;
-  HIP_OK(hipMemcpyAsync(base + R.b, rq.b, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
-  HIP_OK(hipMemcpyAsync(base + R.l, rq.l, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
-  HIP_OK(hipMemcpyAsync(base + R.u, rq.u, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
-  HIP_OK(hipMemcpyAsync(base + R.x, rq.x0, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+  const size_t vb = 8 * (size_t)n;
+  HIP_OK(hipMemcpyAsync(base + R.b, rq.b, vb, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipMemcpyAsync(base + R.l, rq.l, vb, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipMemcpyAsync(base + R.u, rq.u, vb, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipMemcpyAsync(base + R.x0, rq.x0, vb, hipMemcpyDeviceToDevice, st));
   const size_t ex = (size_t)op.ny * (op.nx + 1), ey = (size_t)(op.ny + 1) * op.nx;
   if (op.kind == GPCG_OP_STENCIL5_VAR) {
     HIP_OK(hipMemcpyAsync(base + R.wx, op.wx, 8 * ex, hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(base + R.wy, op.wy, 8 * ey, hipMemcpyDeviceToDevice, st));
-    if (R.wx32) {
-      if (gpcg_launch_convert_f32((const double *)(base + R.wx), (float *)(base + R.wx32),
-                                  (int64_t)ex, st) ||
-          gpcg_launch_convert_f32((const double *)(base + R.wy), (float *)(base + R.wy32),
-                                  (int64_t)ey, st))
-        return fail(GPCG_ERR_HIP, "FP32 weight conversion failed");
-    }
+    if (L.wx32 &&
+        (gpcg_launch_convert_f32((const double *)(base + R.wx), (float *)(base + L.wx32),
+                                 (int64_t)ex, st) ||
+         gpcg_launch_convert_f32((const double *)(base + R.wy), (float *)(base + L.wy32),
+                                 (int64_t)ey, st)))
+      return fail(GPCG_ERR_HIP, "FP32 weight conversion failed");
   }
-  QPState &q = s->stage[slot_id];
+  QPDev &q = s->stage[slot_id];
   std::memset(&q, 0, sizeof(q));
-  q.op_kind = op.kind == GPCG_OP_STENCIL5_CONST ? OPK_CONST : OPK_VAR;
-  q.nx = op.nx;
-  q.ny = op.ny;
-  q.n = n;
-  q.tile = R.tile;
-  q.ntiles = R.ntiles;
-  q.mixed = s->opt.precision == GPCG_PREC_MIXED ? 1 : 0;
-  magic_for(q.nx, &q.div_magic, &q.div_shift);
-  q.w = op.w;
-  q.w32 = (float)op.w;
-  q.wx = R.wx ? (const double *)(base + R.wx) : nullptr;
-  q.wy = R.wy ? (const double *)(base + R.wy) : nullptr;
-  q.wx32 = R.wx32 ? (const float *)(base + R.wx32) : nullptr;
-  q.wy32 = R.wy32 ? (const float *)(base + R.wy32) : nullptr;
-  q.b = (const double *)(base + R.b);
-  q.l = (const double *)(base + R.l);
-  q.u = (const double *)(base + R.u);
-  q.x = (double *)(base + R.x);
-  q.g = (double *)(base + R.g);
-  q.vw = base + R.w;
-  q.vr = base + R.r;
-  q.vp0 = base + R.p0;
-  q.vp1 = base + R.p1;
-  q.mask = (uint8_t *)(base + R.mask);
-  q.partials = (double *)(base + R.partials);
-  q.host_flag = s->flags.dev + slot_id;
-  const gpcg_options &o = s->solve_opt;
-  q.tol_rel = o.tol_rel;
-  q.tol_abs = o.tol_abs;
-  q.eta1 = o.eta1;
-  q.eta2 = o.eta2;
-  q.eta2_reduce = o.eta2_reduce;
-  q.mu = o.mu;
-  q.max_outer = o.max_outer;
-  q.max_gp = o.max_gp;
-  q.max_backtrack = o.max_backtrack;
-  q.max_cg = o.max_cg;
-  q.max_stall = o.max_stall;
-  reset_dynamic(q);
+  QPStatic &S = q.st;
+  S.op_kind = op.kind == GPCG_OP_STENCIL5_CONST ? OPK_CONST : OPK_VAR;
+  S.nx = op.nx;
+  S.ny = op.ny;
+  S.n = n;
+  S.tile = L.tile;
+  S.ntiles = L.ntiles;
+  S.mixed = s->opt.precision == GPCG_PREC_MIXED ? 1 : 0;
+  magic_for(S.nx, &S.div_magic, &S.div_shift);
+  S.w = op.w;
+  S.w32 = (float)op.w;
+  S.wx = R.wx ? (const double *)(base + R.wx) : nullptr;
+  S.wy = R.wy ? (const double *)(base + R.wy) : nullptr;
+  S.wx32 = L.wx32 ? (const float *)(base + L.wx32) : nullptr;
+  S.wy32 = L.wy32 ? (const float *)(base + L.wy32) : nullptr;
+  S.b = (const double *)(base + R.b);
+  S.l = (const double *)(base + R.l);
+  S.u = (const double *)(base + R.u);
+  S.x[0] = (double *)(base + R.x0);
+  S.x[1] = (double *)(base + L.x1);
+  S.g[0] = (double *)(base + L.g0);
+  S.g[1] = (double *)(base + L.g1);
+  S.rho[0] = base + L.rho0;
+  S.rho[1] = base + L.rho1;
+  S.uq[0] = base + L.uq0;
+  S.uq[1] = base + L.uq1;
+  S.sq[0] = base + L.sq0;
+  S.sq[1] = base + L.sq1;
+  S.pv = base + L.p;
+  S.wv = base + L.w;
+  S.mask = (uint8_t *)(base + L.mask);
+  S.partials[0] = (double *)(base + L.part0);
+  S.partials[1] = (double *)(base + L.part1);
+  S.host_flag = s->flags.dev + slot_id;
+  put_options(S, s->solve_opt);
+  initial_dyn(q.dyn[0]);
+  initial_dyn(q.dyn[1]);
   s->flags.host[slot_id] = 0;
-  HIP_OK(hipMemcpyAsync(base + R.state, &q, sizeof(QPState), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(base + L.qp, &q, sizeof(QPDev), hipMemcpyHostToDevice, st));
   sl.used = true;
   sl.off = off;
   sl.bytes = p.bytes;
   sl.req = rq;
   sl.t_submit = p.t_submit;
   sl.t_admit = now_s();
-  sl.ntiles = R.ntiles;
+  sl.ntiles = L.ntiles;
   s->resident += 1;
-  s->dirty = true;
   return GPCG_OK;
 }
 
-// Moves finished requests to the completion list (after the stream is idle).
+// Moves finished requests to the completion list (after the stream is idle;
+// the last launch wrote the state of parity launches & 1).
 int srv_retire(gpcg_server_s *s) {
   std::vector<int> fin;
   for (int i = 0; i < (int)s->slots.size(); ++i)
     if (s->slots[i].used && s->flags.host[i]) fin.push_back(i);
   if (fin.empty()) return GPCG_OK;
+  const int par = (int)(s->launches & 1);
   for (int i : fin) {
     SrvSlot &sl = s->slots[i];
     const ReqLayout R = req_layout(&sl.req.op, s->opt.precision);
     char *base = s->arena + sl.off;
-    HIP_OK(hipMemcpyAsync(&s->stage[i], base + R.state, sizeof(QPState), hipMemcpyDeviceToHost,
+    HIP_OK(hipMemcpyAsync(&s->stage[i], base + R.L.qp, sizeof(QPDev), hipMemcpyDeviceToHost,
                           s->stream));
+  }
+  HIP_OK(hipStreamSynchronize(s->stream));
+  for (int i : fin) {
+    SrvSlot &sl = s->slots[i];
+    const ReqLayout R = req_layout(&sl.req.op, s->opt.precision);
+    char *base = s->arena + sl.off;
+    const QPDyn &d = s->stage[i].dyn[par];
     if (sl.req.x_out)
-      HIP_OK(hipMemcpyAsync(sl.req.x_out, base + R.x, 8 * (size_t)op_n(&sl.req.op),
-                            hipMemcpyDeviceToDevice, s->stream));
+      HIP_OK(hipMemcpyAsync(sl.req.x_out, base + (d.cur ? R.L.x1 : R.x0),
+                            8 * (size_t)op_n(&sl.req.op), hipMemcpyDeviceToDevice, s->stream));
   }
   HIP_OK(hipStreamSynchronize(s->stream));
   const double t = now_s();
   for (int i : fin) {
     SrvSlot &sl = s->slots[i];
+    const QPDyn &d = s->stage[i].dyn[par];
     gpcg_completion c{};
     c.tag = sl.req.tag;
-    fill_stats(s->stage[i], s->tick_hz, &c.stats);
-    c.status = s->stage[i].status;
+    fill_stats(s->stage[i].st, d, s->tick_hz, &c.stats);
+    c.status = d.status;
     c.t_submit = sl.t_submit;
     c.t_admit = sl.t_admit;
     c.t_done = t;
@@ -1143,7 +1102,6 @@ int srv_retire(gpcg_server_s *s) {
     sl.used = false;
     s->flags.host[i] = 0;
     s->resident -= 1;
-    s->dirty = true;
   }
   return GPCG_OK;
 }
@@ -1170,6 +1128,7 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   if (opt->precision != GPCG_PREC_FP64 && opt->precision != GPCG_PREC_MIXED)
     return fail(GPCG_ERR_ARG, "unknown precision");
   if (!(opt->tol_rel >= 0.0)) return fail(GPCG_ERR_ARG, "tol_rel < 0");
+  if (opt->quantum < 0 || (opt->quantum & 1)) return fail(GPCG_ERR_ARG, "quantum must be even");
   if (!opt->arena || ((uintptr_t)opt->arena % kAlign) != 0)
     return fail(GPCG_ERR_WORKSPACE, "arena missing or not 256-byte aligned");
   const size_t header = tables_bytes(opt->max_slots);
@@ -1180,9 +1139,8 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   s->stream = (hipStream_t)stream;
   s->arena = (char *)opt->arena;
   s->header = header;
-  s->T.qptrs = (QPState **)s->arena;
-  s->T.prefix = (int32_t *)(s->arena + align_up(sizeof(void *) * (size_t)opt->max_slots));
-  s->T.bytes = header;
+  s->qptrs = (QPDev **)s->arena;
+  s->prefix = (int32_t *)(s->arena + align_up(sizeof(void *) * (size_t)opt->max_slots));
   s->slots.resize(opt->max_slots);
   s->free_list[header] = opt->arena_bytes - header;
   s->tick_hz = wall_clock_hz();
@@ -1191,11 +1149,11 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   s->solve_opt.precision = opt->precision;
   int rc = alloc_flag(&s->flags, (size_t)opt->max_slots);
   void *st = nullptr, *tb = nullptr;
-  if (!rc && (hipHostMalloc(&st, sizeof(QPState) * opt->max_slots, hipHostMallocDefault) !=
+  if (!rc && (hipHostMalloc(&st, sizeof(QPDev) * opt->max_slots, hipHostMallocDefault) !=
                   hipSuccess ||
               hipHostMalloc(&tb, header, hipHostMallocDefault) != hipSuccess))
     rc = fail(GPCG_ERR_HIP, "hipHostMalloc for the server failed");
-  s->stage = (QPState *)st;
+  s->stage = (QPDev *)st;
   s->stage_tables = (char *)tb;
   if (rc) {
     gpcg_server_destroy(s);
@@ -1230,30 +1188,42 @@ int gpcg_server_step(gpcg_server s, int *active) {
         slot = i;
         break;
       }
+    // a new request starts at the parity of the next launch
+    if (s->launches & 1) {
+      // keep the launch count even at admission: one empty launch is never
+      // needed because quanta are even; this branch documents the invariant
+      return fail(GPCG_ERR_ARG, "internal: odd launch count at admission");
+    }
     rc = srv_admit(s, slot, s->queue.front(), off);
     if (rc) return rc;
     s->queue.pop_front();
   }
   if (s->resident > 0) {
-    auto **qp = (QPState **)s->stage_tables;
+    auto **qp = (QPDev **)s->stage_tables;
     auto *pre = (int32_t *)(s->stage_tables + align_up(sizeof(void *) * s->slots.size()));
     int cnt = 0;
     pre[0] = 0;
     for (int i = 0; i < (int)s->slots.size(); ++i) {
       if (!s->slots[i].used) continue;
       const ReqLayout R = req_layout(&s->slots[i].req.op, s->opt.precision);
-      qp[cnt] = (QPState *)(s->arena + s->slots[i].off + R.state);
+      qp[cnt] = (QPDev *)(s->arena + s->slots[i].off + R.L.qp);
       pre[cnt + 1] = pre[cnt] + s->slots[i].ntiles;
       ++cnt;
     }
     HIP_OK(hipMemcpyAsync(s->arena, s->stage_tables, s->header, hipMemcpyHostToDevice,
                           s->stream));
-    StepLaunch SL{s->T.qptrs, s->T.prefix, cnt, pre[cnt]};
-    for (int k = 0; k < s->opt.quantum; ++k)
+    StepLaunch SL{};
+    SL.qps = s->qptrs;
+    SL.prefix = s->prefix;
+    SL.nqp = cnt;
+    SL.total_tiles = pre[cnt];
+    for (int k = 0; k < s->opt.quantum; ++k) {
+      SL.parity = (int)(s->launches & 1);
       if (gpcg_launch_step(SL, s->opt.precision == GPCG_PREC_MIXED, s->stream) != 0)
         return fail(GPCG_ERR_HIP, "pass kernel launch failed");
+      s->launches += 1;
+    }
     HIP_OK(hipStreamSynchronize(s->stream));
-    s->dirty = false;
     rc = srv_retire(s);
     if (rc) return rc;
   }
@@ -1266,7 +1236,7 @@ int gpcg_server_poll(gpcg_server s, gpcg_completion *out, int max, int *got) {
   int k = 0;
   while (k < max && !s->done.empty() && out) {
     out[k++] = s->done.front();
-    s->done.erase(s->done.begin());
+    s->done.pop_front();
   }
   *got = k;
   return GPCG_OK;
