@@ -105,18 +105,29 @@ typedef struct {
   int32_t precision;   /* GPCG_PREC_*                                         */
   int32_t free_set;    /* GPCG_FREESET_*                                      */
   int32_t tile;        /* unknowns per workgroup and pass (multiple of 256);
-                          0 = the library's tuned choice for this size        */
+                          0 = 256 (one unknown per thread)                    */
   int32_t chunk;       /* device passes per host check; 0 = library choice    */
   int32_t use_graph;   /* 1 = replay chunks as HIP graphs (default), 0 = launch */
   int32_t max_stall;   /* stop as GPCG_STAGNATED when ||P grad q|| after a
                           projected search has not improved on its best value
                           for this many consecutive GPCG iterations (the
                           rounding floor of FP64 has been reached)            */
+  int32_t form;        /* launch form: GPCG_FORM_AUTO (fused when the grid
+                          has at most 1024 tiles of 256 unknowns, else split),
+                          GPCG_FORM_FUSED or GPCG_FORM_SPLIT; the answer is
+                          bitwise the same in every form                     */
 } gpcg_options;
+
+#define GPCG_FORM_AUTO 0
+#define GPCG_FORM_FUSED 1 /* one launch per pass; every workgroup folds the
+                             previous pass's sums into the state itself       */
+#define GPCG_FORM_SPLIT 2 /* two launches per pass: a transition kernel (one
+                             workgroup per QP), then a data kernel            */
 
 /* Fills the defaults: tol_rel 1e-8, tol_abs 0, eta1 0.1, eta2 0.05,
  * eta2_reduce 0.1, mu 0.01, max_outer 100000, max_gp 50, max_backtrack 60,
- * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25. */
+ * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
+ * form GPCG_FORM_AUTO. */
 void gpcg_options_default(gpcg_options *opt);
 
 /* ------------------------------------------------------------------- stats */

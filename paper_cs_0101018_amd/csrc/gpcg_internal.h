@@ -58,24 +58,27 @@ struct QPStatic {
   void *rho[2], *uq[2], *sq[2];  // CG residual, A*residual, A*direction (FP64/FP32)
   void *pv, *wv;                 // CG direction and iterate
   uint8_t *mask;                 // free set of the current CG phase
-  double *partials[2];           // [ntiles][kNP] per launch parity
   int32_t *host_flag;            // device view of a mapped host word, or null
   double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
 };
 
-// The scalar state machine (one copy per launch parity).
-struct QPDyn {
+// The scalar state machine: the part the transition reads and writes.
+struct QPCore {
   int32_t phase, ctx, status, pending;  // pending: partials of `phase` await reduction
-  int32_t cur, cgpar, first, ps_accepted;
-  int32_t gp_j, bt, gp_accepts, cg_j;
-  int32_t max_cg_eff, stall, x0_projected, pad0;
+  int32_t cur, first, ps_accepted, gp_j;
+  int32_t bt, gp_accepts, cg_j, max_cg_eff;
+  int32_t stall, x0_projected, outer_iters, gp_iters;
+  int32_t cg_iters, backtracks, face_repeats, cg_phases;
   double tau, pg0, pgn, q, best_pg;
   double alpha, gp_decmax;
   double eta, cg_alpha, cg_beta, gamma, cg_decmax;
   int64_t m_free, n_lower, n_upper, n_nonbinding;
-  int32_t outer_iters, gp_iters, cg_iters, backtracks;
-  int32_t face_repeats, cg_phases, pad1, pad2;
   int64_t passes, cg_free_rows;
+};
+
+// One copy of the state per launch parity: the core plus per-pass counters.
+struct QPDyn {
+  QPCore c;
   int64_t pass_count[PH_COUNT];
   uint64_t t_last;
   uint64_t t_bucket[4];
@@ -87,6 +90,21 @@ struct QPDev {
   uint32_t counter;  // persistent form: arrivals (monotonic)
   uint32_t pad[63];
 };
+
+// The tile slots of a QP follow its QPDev at a fixed offset, laid out
+// [max(ntiles, kBlock)][2 parities][kNP] doubles, so a workgroup can fetch
+// the state and its slot in one round trip (slot tid always exists).
+constexpr size_t kQPDevBytes = (sizeof(QPDev) + 255) / 256 * 256;
+
+__host__ __device__ inline double *tile_slots(QPDev *q) {
+  return reinterpret_cast<double *>(reinterpret_cast<char *>(q) + kQPDevBytes);
+}
+__host__ __device__ inline const double *tile_slots(const QPDev *q) {
+  return reinterpret_cast<const double *>(reinterpret_cast<const char *>(q) + kQPDevBytes);
+}
+__host__ __device__ inline size_t tile_slot_bytes(int ntiles) {
+  return sizeof(double) * 2 * kNP * (size_t)(ntiles > kBlock ? ntiles : kBlock);
+}
 
 struct StepLaunch {
   QPDev *single;           // one QP: its state (tables unused)
@@ -109,8 +127,14 @@ struct PersistLaunch {
 }  // namespace gpcg
 
 extern "C++" {
-void *gpcg_step_kernel_ptr(int mixed);
-int gpcg_launch_step(const gpcg::StepLaunch &L, int mixed, void *stream);
+// spec: the launch holds only stencil QPs with 256-unknown tiles, which may use
+// the variant that loads CG operands before the state is known.
+void *gpcg_step_kernel_ptr(int mixed, int spec);
+int gpcg_launch_step(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
+// Split form: a transition kernel (grid = QPs) then a data kernel (grid = tiles).
+void *gpcg_transition_kernel_ptr();
+void *gpcg_pass_kernel_ptr(int mixed, int spec);
+int gpcg_launch_split(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
 int gpcg_launch_spmv(const gpcg::QPDev *dqp, int64_t n, const void *v, void *y,
                      const uint8_t *mask, int f32, void *stream);
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,

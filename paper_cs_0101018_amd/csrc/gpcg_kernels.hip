@@ -178,24 +178,62 @@ __device__ __forceinline__ Pair apply_row2(const OpView<double> &A, int64_t k, F
 
 // ---------------------------------------------------------------- reductions
 
-// Sum of N values over the workgroup; the result is valid in thread 0.  The
-// order of additions is fixed (butterfly in each wave64, then waves 0..3).
-template <typename R, int N>
-__device__ __forceinline__ void block_sum(R (&v)[N]) {
+// Cross-lane moves with DPP (gfx9 encodings; every source lane is active and
+// in range for these patterns) and lane reads.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_f32(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane.  Fixed
+// order: lane ^ 1, lane ^ 2 (quad permutes), the other quad of the half-row,
+// the other half of the row, then the four rows (lanes 0, 16, 32, 48).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  v += dpp_f32<0x141>(v);
+  v += dpp_f32<0x140>(v);
+  return (lane_f32(v, 0) + lane_f32(v, 16)) + (lane_f32(v, 32) + lane_f32(v, 48));
+}
+
+// Sum of v[0..N) over the workgroup, valid in thread 0 (waves added in the
+// order 0..3).  Must be called by every thread, in uniform control flow.  The
+// LDS scratch is reused by the next call of the same instantiation: callers
+// separate two such calls by a barrier.
+template <typename R, int N, int M>
+__device__ __forceinline__ void block_sum(R (&v)[M]) {
+  static_assert(N <= M, "slot count");
   __shared__ R sh[kBlock / 64][N];
+  const int wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < N; ++k) sh[wave][k] = v[k];
+  for (int k = 0; k < N; ++k) {
+    const R w = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) sh[wave][k] = w;
+  }
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
-  __syncthreads();
 }
 
 // Map the launch index of a workgroup to a tile so that consecutive tiles land
@@ -214,48 +252,102 @@ __device__ __forceinline__ bool f32_slots(int mixed, int phase) {
   return mixed && (phase == PH_CG_INIT || phase == PH_CG_ITER);
 }
 
-// Reduces this workgroup's per-thread sums into partials[tile] (thread 0).
-__device__ __forceinline__ void write_partial(double *part, bool f32, int tile, double (&acc)[kNP],
-                                              float (&accf)[2]) {
-  block_sum<double, kNP>(acc);
+// Number of reduction slots a pass fills.
+__device__ __forceinline__ int nslots(int phase) {
+  switch (phase) {
+    case PH_GP_ALPHA: case PH_CG_ITER: return 2;
+    case PH_CG_INIT: return 3;
+    default: return kNP;
+  }
+}
+
+// Workgroup sum of the slots a pass fills (valid in thread 0); FP32 slots of
+// the mixed CG passes are summed in FP32 and stored widened.
+__device__ __forceinline__ void block_slots(int ns, bool f32, double (&acc)[kNP],
+                                            float (&accf)[2]) {
   if (f32) {
     block_sum<float, 2>(accf);
+    if (ns == 3) block_sum<double, 3>(acc);  // slot 2 is a count
     if (threadIdx.x == 0) {
       acc[0] = (double)accf[0];
       acc[1] = (double)accf[1];
     }
-  }
-  if (threadIdx.x == 0) {
-    double *slot = part + (int64_t)tile * kNP;
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) slot[k] = acc[k];
+  } else if (ns == 2) {
+    block_sum<double, 2>(acc);
+  } else if (ns == 3) {
+    block_sum<double, 3>(acc);
+  } else {
+    block_sum<double, kNP>(acc);
   }
 }
 
-// Sums the ntiles slots of `part` in tile order; result in thread 0's res.
-__device__ __forceinline__ void sum_partials(const double *part, int ntiles, bool f32,
-                                             double (&res)[kNP]) {
-  double v[kNP];
-  float vf[2] = {0.0f, 0.0f};
+// Reduces this workgroup's per-thread sums into the tile's slot of parity
+// `par` (thread 0 writes the ns slots the pass fills).
+__device__ __forceinline__ void write_partial(double *slots, int par, int phase, bool f32,
+                                              int tile, double (&acc)[kNP], float (&accf)[2]) {
+  const int ns = nslots(phase);
+  block_slots(ns, f32, acc, accf);
+  if (threadIdx.x == 0) {
+    double *slot = slots + ((int64_t)tile * 2 + par) * kNP;
+    for (int k = 0; k < ns; ++k) slot[k] = acc[k];
+  }
+}
+
+// Loads slot `tid` of parity par (always present) ahead of time.
+__device__ __forceinline__ void prefetch_slot(const double *slots, int par, double (&pf)[kNP]) {
+  const double *slot = slots + ((int64_t)threadIdx.x * 2 + par) * kNP;
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) v[k] = 0.0;
-  for (int t = threadIdx.x; t < ntiles; t += kBlock) {
-    const double *slot = part + (int64_t)t * kNP;
+  for (int k = 0; k < kNP; ++k) pf[k] = slot[k];
+}
+
+// Adds slots t = tid + 256, tid + 512, ... (in that order) of parity par to
+// res / vf, keeping D slots in flight.
+template <int NS, int D = (NS <= 3 ? 8 : 2)>
+__device__ __forceinline__ void sum_slot_tail(const double *slots, int par, int ntiles,
+                                              double (&res)[kNP], float (&vf)[2]) {
+  int t = (int)threadIdx.x + kBlock;
+  for (; t + (D - 1) * kBlock < ntiles; t += D * kBlock) {
+    double buf[D][NS];
 #pragma unroll
-    for (int k = 0; k < kNP; ++k) v[k] += slot[k];
+    for (int u = 0; u < D; ++u)
+#pragma unroll
+      for (int k = 0; k < NS; ++k) buf[u][k] = slots[((int64_t)(t + u * kBlock) * 2 + par) * kNP + k];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) res[k] += buf[u][k];
+      vf[0] += (float)buf[u][0];
+      vf[1] += (float)buf[u][1];
+    }
+  }
+  for (; t < ntiles; t += kBlock) {
+    const double *slot = slots + ((int64_t)t * 2 + par) * kNP;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) res[k] += slot[k];
     vf[0] += (float)slot[0];
     vf[1] += (float)slot[1];
   }
-  block_sum<double, kNP>(v);
-  if (f32) {
-    block_sum<float, 2>(vf);
-    if (threadIdx.x == 0) {
-      v[0] = (double)vf[0];
-      v[1] = (double)vf[1];
-    }
-  }
+}
+
+// Sums the ntiles slots of parity par that pass `phase` filled, in tile
+// order (thread tid takes tiles tid, tid + 256, ...; slot tid prefetched in
+// pf); the result is valid in thread 0's res.
+__device__ __forceinline__ void sum_partials(const double *slots, int par, int ntiles, int phase,
+                                             bool f32, const double (&pf)[kNP],
+                                             double (&res)[kNP]) {
+  const int ns = nslots(phase);
+  float vf[2];
+  const bool mine = (int)threadIdx.x < ntiles;
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) res[k] = v[k];
+  for (int k = 0; k < kNP; ++k) res[k] = (mine && k < ns) ? pf[k] : 0.0;
+  vf[0] = mine ? (float)pf[0] : 0.0f;
+  vf[1] = mine ? (float)pf[1] : 0.0f;
+  if (ntiles > kBlock) {
+    if (ns == 2) sum_slot_tail<2>(slots, par, ntiles, res, vf);
+    else if (ns == 3) sum_slot_tail<3>(slots, par, ntiles, res, vf);
+    else sum_slot_tail<kNP>(slots, par, ntiles, res, vf);
+  }
+  block_slots(ns, f32, res, vf);
 }
 
 // ------------------------------------------------------------ the passes
@@ -273,7 +365,8 @@ __device__ __forceinline__ void face_acc(double x, double l, double u, double g,
 }
 
 template <typename CT>
-__device__ void run_pass(const QPStatic *__restrict__ S, const QPDyn &d, int phase, int64_t k0,
+__device__ void run_pass(const QPStatic *__restrict__ S, const QPCore &d, int phase, int lpar,
+                         int64_t k0,
                          int64_t k1, double (&acc)[kNP], float (&accf)[2]) {
   const double *__restrict__ l = S->l;
   const double *__restrict__ u = S->u;
@@ -340,10 +433,11 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const QPDyn &d, int pha
     case PH_CG_INIT: {
       const OpView<CT> A = op_view<CT>(S);
       uint8_t *__restrict__ mask = S->mask;
-      CT *__restrict__ r0 = (CT *)S->rho[0];
-      CT *__restrict__ u0 = (CT *)S->uq[0];
-      CT *__restrict__ r1 = (CT *)S->rho[1];
-      CT *__restrict__ u1 = (CT *)S->uq[1];
+      // the first CG iteration runs in the next launch, which reads parity lpar ^ 1
+      CT *__restrict__ r0 = (CT *)S->rho[lpar ^ 1];
+      CT *__restrict__ u0 = (CT *)S->uq[lpar ^ 1];
+      CT *__restrict__ r1 = (CT *)S->rho[lpar];
+      CT *__restrict__ u1 = (CT *)S->uq[lpar];
       CT *__restrict__ s0 = (CT *)S->sq[0];
       CT *__restrict__ s1 = (CT *)S->sq[1];
       CT *__restrict__ p = (CT *)S->pv;
@@ -385,7 +479,7 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const QPDyn &d, int pha
     case PH_CG_ITER: {
       const OpView<CT> A = op_view<CT>(S);
       const uint8_t *__restrict__ mask = S->mask;
-      const int par = d.cgpar;
+      const int par = lpar;  // CG buffers alternate with the launch parity
       const bool first = d.first != 0;
       const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
       const CT *__restrict__ ro = (const CT *)S->rho[par];
@@ -463,13 +557,13 @@ __device__ __forceinline__ int time_bucket(int phase) {
   }
 }
 
-__device__ __forceinline__ void finish(QPDyn &d, int status) {
+__device__ __forceinline__ void finish(QPCore &d, int status) {
   d.status = status;
   d.phase = PH_DONE;
 }
 
 // A gradient-projection phase begins: y_0 = x_k (Algorithm GPCG, first bullet).
-__device__ __forceinline__ void start_gp(QPDyn &d) {
+__device__ __forceinline__ void start_gp(QPCore &d) {
   d.gp_j = 1;
   d.gp_decmax = -INFINITY;
   d.gp_accepts = 0;
@@ -478,7 +572,7 @@ __device__ __forceinline__ void start_gp(QPDyn &d) {
 
 // The gradient-projection phase ends: termination test, then CG with the
 // initial eta2 (reset whenever a gradient-projection phase runs).
-__device__ __forceinline__ void end_gp(const QPStatic *S, QPDyn &d) {
+__device__ __forceinline__ void end_gp(const QPStatic *S, QPCore &d) {
   if (d.pgn <= d.tau) {
     finish(d, GPCG_OK);
     return;
@@ -488,14 +582,14 @@ __device__ __forceinline__ void end_gp(const QPStatic *S, QPDyn &d) {
 }
 
 // Projected search along d_k = Z_k w: alpha = 1, 1/2, 1/4, ... (eq. cglsstop2).
-__device__ __forceinline__ void start_ps(QPDyn &d) {
+__device__ __forceinline__ void start_ps(QPCore &d) {
   d.alpha = 1.0;
   d.bt = 0;
   d.ps_accepted = 0;
   d.phase = PH_PS_TRIAL;
 }
 
-__device__ __forceinline__ void set_face(QPDyn &d, const double *R) {
+__device__ __forceinline__ void set_face(QPCore &d, const double *R) {
   d.pgn = sqrt(R[0]);
   d.n_lower = (int64_t)R[1];
   d.n_upper = (int64_t)R[2];
@@ -505,13 +599,9 @@ __device__ __forceinline__ void set_face(QPDyn &d, const double *R) {
 
 // Folds the reduced results R of pass d.phase into the state and selects the
 // next pass.  Runs in one thread of every workgroup on identical inputs.
-__device__ void transition(const QPStatic *S, QPDyn &d, const double *R) {
+__device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
   const int ph = d.phase;
-  const uint64_t now = wall_clock64();
-  if (d.t_last) d.t_bucket[time_bucket(ph)] += now - d.t_last;
-  d.t_last = now;
   d.passes += 1;
-  d.pass_count[ph] += 1;
   switch (ph) {
     case PH_INIT:
       if (R[6] > 0.0) { finish(d, GPCG_ERR_NAN); break; }
@@ -571,7 +661,6 @@ __device__ void transition(const QPStatic *S, QPDyn &d, const double *R) {
       d.cg_decmax = -INFINITY;
       d.max_cg_eff = S->max_cg > 0 ? S->max_cg : (int32_t)m;
       d.first = 1;
-      d.cgpar = 0;
       d.gamma = R[0];
       if (!(d.gamma > 0.0)) start_ps(d);  // r_k = 0: the CG direction is 0
       else if (!(R[1] > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
@@ -589,7 +678,6 @@ __device__ void transition(const QPStatic *S, QPDyn &d, const double *R) {
       const bool stop = (R[0] == 0.0) || (d.cg_j >= 2 && dec <= d.eta * d.cg_decmax) ||
                         (d.cg_j >= d.max_cg_eff);  // eq. (cgstop1)
       if (dec > d.cg_decmax) d.cg_decmax = dec;
-      d.cgpar ^= 1;
       d.first = 0;
       if (stop) start_ps(d);
       else {
@@ -642,6 +730,20 @@ __device__ void transition(const QPStatic *S, QPDyn &d, const double *R) {
   }
 }
 
+// Runs the transition of the pending pass on a register copy of the core and
+// books the pass in the per-phase counters (thread 0, state in LDS).
+__device__ __forceinline__ void advance(const QPStatic *S, QPDyn &sd, const double *R,
+                                       uint64_t now) {
+  const int ph = sd.c.phase;
+  QPCore c = sd.c;
+  transition(S, c, R);
+  sd.c = c;
+  if (ph >= 0 && ph < PH_COUNT) sd.pass_count[ph] += 1;
+  const int bk = time_bucket(ph);
+  if (sd.t_last) sd.t_bucket[bk] += now - sd.t_last;
+  sd.t_last = now;
+}
+
 // --------------------------------------------------------- state transfer
 
 constexpr int kDynWords = (int)(sizeof(QPDyn) / 4);
@@ -656,10 +758,93 @@ __device__ __forceinline__ void copy_dyn(const QPDyn *src, QPDyn *dst) {
 
 // ------------------------------------------------------------------ kernels
 
+// ------------------------------------------- speculative CG operand loads
+
+// Operands of one CG iteration at unknown k of a stencil operator.  They
+// depend only on k and on the launch parity (the CG buffers alternate with
+// it), so a workgroup can load them before it knows the state and hide their
+// latency behind the slot reduction and the transition.
+template <typename CT>
+struct CGOperands {
+  CT r, u, s, p, w;      // rho, A rho, A p (previous), p, w at k
+  CT rn[4], un[4], sn[4];  // rho, A rho, A p at the W, E, S, N neighbours (0 outside)
+  CT wt[4];              // edge weights W, E, S, N (variable stencil)
+  int m;                 // free-set mask at k
+};
+
+template <typename CT>
+__device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t k,
+                                            CGOperands<CT> &P) {
+  const OpView<CT> A = op_view<CT>(S);
+  const CT *__restrict__ ro = (const CT *)S->rho[lpar];
+  const CT *__restrict__ uo = (const CT *)S->uq[lpar];
+  const CT *__restrict__ so = (const CT *)S->sq[lpar];
+  P.m = S->mask[k];
+  P.r = ro[k];
+  P.u = uo[k];
+  P.s = so[k];
+  P.p = ((const CT *)S->pv)[k];
+  P.w = ((const CT *)S->wv)[k];
+  const int32_t nx = A.nx;
+  const int32_t j = (int32_t)(((uint64_t)k * A.magic) >> A.shift);
+  const int32_t i = (int32_t)(k - (int64_t)j * nx);
+  const int64_t nb[4] = {k - 1, k + 1, k - nx, k + nx};
+  const bool has[4] = {i > 0, i < nx - 1, j > 0, j < A.ny - 1};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    P.rn[q] = has[q] ? ro[nb[q]] : CT(0);
+    P.un[q] = has[q] ? uo[nb[q]] : CT(0);
+    P.sn[q] = has[q] ? so[nb[q]] : CT(0);
+  }
+  if (A.kind == OPK_VAR) {
+    const int64_t ex = (int64_t)j * (nx + 1) + i;
+    const int64_t ey = (int64_t)j * nx + i;
+    P.wt[0] = A.wx[ex];
+    P.wt[1] = A.wx[ex + 1];
+    P.wt[2] = A.wy[ey];
+    P.wt[3] = A.wy[ey + nx];
+  }
+}
+
+// The CG iteration of run_pass for one unknown, on prefetched operands.  Same
+// formulas in the same order as the generic path (bitwise equal results).
+template <typename CT>
+__device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCore &d, int lpar,
+                                                   int64_t k, const CGOperands<CT> &P, CT &gam,
+                                                   CT &del) {
+  if (!P.m) return;
+  const bool first = d.first != 0;
+  const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
+  const CT sk = first ? P.u : fmaT<CT>(be, P.s, P.u);
+  const CT r1 = fmaT<CT>(-al, sk, P.r);
+  const CT pk = first ? P.r : fmaT<CT>(be, P.p, P.r);
+  ((CT *)S->wv)[k] = fmaT<CT>(al, pk, P.w);
+  ((CT *)S->pv)[k] = pk;
+  ((CT *)S->sq[lpar ^ 1])[k] = sk;
+  ((CT *)S->rho[lpar ^ 1])[k] = r1;
+  CT v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const CT sq = first ? P.un[q] : fmaT<CT>(be, P.sn[q], P.un[q]);
+    v[q] = fmaT<CT>(-al, sq, P.rn[q]);
+  }
+  CT u1;
+  if (S->op_kind == OPK_CONST) {
+    const OpView<CT> A = op_view<CT>(S);
+    u1 = A.w * ((r1 - v[0]) + (r1 - v[1]) + ((r1 - v[2]) + (r1 - v[3])));
+  } else {
+    u1 = (P.wt[0] * (r1 - v[0]) + P.wt[1] * (r1 - v[1])) +
+         (P.wt[2] * (r1 - v[2]) + P.wt[3] * (r1 - v[3]));
+  }
+  ((CT *)S->uq[lpar ^ 1])[k] = u1;
+  gam = fmaT<CT>(r1, r1, gam);
+  del = fmaT<CT>(r1, u1, del);
+}
+
 // Stepped form: one launch = one pass of every QP of the launch; one
 // workgroup = one tile.  Every workgroup first folds the previous launch's
 // partial sums into its own copy of the state.
-template <typename CT>
+template <typename CT, bool SPEC>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ int s_fresh_done;
@@ -681,22 +866,32 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   }
   const QPStatic *S = &q->st;
   const int par = L.parity;
+  double *slots = tile_slots(q);
+  double pf[kNP];
+  prefetch_slot(slots, par, pf);  // issued together with the state load
+  const int ntiles = S->ntiles, mixed = S->mixed;
+  const uint64_t clk = wall_clock64();
+  // SPEC launches hold only stencil QPs with one unknown per thread
+  const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
+  const bool own = SPEC && kk < S->n;
+  CGOperands<CT> P;
+  if (own) cg_prefetch<CT>(S, par, kk, P);
   copy_dyn(&q->dyn[par], &sd);
   __syncthreads();
-  if (sd.pending) {
+  if (sd.c.pending) {
     double R[kNP];
-    sum_partials(S->partials[par], S->ntiles, f32_slots(S->mixed, sd.phase), R);
+    sum_partials(slots, par, ntiles, sd.c.phase, f32_slots(mixed, sd.c.phase), pf, R);
     if (threadIdx.x == 0) {
-      transition(S, sd, R);
-      s_fresh_done = sd.phase == PH_DONE;
-      sd.pending = sd.phase == PH_DONE ? 0 : 1;
+      advance(S, sd, R, clk);
+      sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
+      s_fresh_done = sd.c.phase == PH_DONE;
     }
   } else if (threadIdx.x == 0) {
     s_fresh_done = 0;
-    sd.pending = sd.phase == PH_DONE ? 0 : 1;
+    sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
   }
   __syncthreads();
-  const int phase = sd.phase;
+  const int phase = sd.c.phase;
   if (phase != PH_DONE) {
     const int64_t k0 = (int64_t)tile * S->tile;
     const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
@@ -704,14 +899,128 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     float accf[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-    run_pass<CT>(S, sd, phase, k0, k1, acc, accf);
-    write_partial(S->partials[par ^ 1], f32_slots(S->mixed, phase), tile, acc, accf);
+    if (SPEC && phase == PH_CG_ITER) {
+      CT gam = CT(0), del = CT(0);
+      if (own) cg_iter_prefetched<CT>(S, sd.c, par, kk, P, gam, del);
+      if (sizeof(CT) == 4) {
+        accf[0] = (float)gam;
+        accf[1] = (float)del;
+      } else {
+        acc[0] = (double)gam;
+        acc[1] = (double)del;
+      }
+    } else {
+      run_pass<CT>(S, sd.c, phase, par, k0, k1, acc, accf);
+    }
+    write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
+    __syncthreads();
   }
   if (tile == 0) {
     copy_dyn(&sd, &q->dyn[par ^ 1]);
     if (threadIdx.x == 0 && s_fresh_done && S->host_flag)
       __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
+}
+
+// ------------------------------------------------------------ split form
+// Large QPs and multi-QP launches run each pass as two launches: a transition
+// kernel (one workgroup per QP) folds the previous pass's slots into the
+// state, then a data kernel with one lean workgroup per tile runs the pass.
+// Tiles, slot sums and formulas are those of the fused form, so a QP gives
+// bitwise the same answer in either form.  Step parity p: the transition reads
+// dyn[p] and slots[p] and writes dyn[p ^ 1]; the data kernel reads dyn[p ^ 1]
+// and writes slots[p ^ 1]; CG buffers alternate with p as in the fused form.
+
+__device__ __forceinline__ QPDev *launch_qp(const StepLaunch &L, int t, int *tile) {
+  if (L.single) {
+    *tile = t;
+    return L.single;
+  }
+  int lo = 0, hi = L.nqp;
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (L.prefix[m] <= t) lo = m;
+    else hi = m;
+  }
+  *tile = t - L.prefix[lo];
+  return L.qps[lo];
+}
+
+// One workgroup per QP of the launch (L.single: grid 1; else grid nqp, QP b).
+__global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
+  __shared__ QPDyn sd;
+  __shared__ int s_fresh_done;
+  QPDev *q = L.single ? L.single : L.qps[blockIdx.x];
+  const QPStatic *S = &q->st;
+  const int par = L.parity;
+  const double *slots = tile_slots(q);
+  double pf[kNP];
+  prefetch_slot(slots, par, pf);
+  const uint64_t clk = wall_clock64();
+  copy_dyn(&q->dyn[par], &sd);
+  __syncthreads();
+  if (sd.c.pending) {
+    double R[kNP];
+    sum_partials(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
+    if (threadIdx.x == 0) {
+      advance(S, sd, R, clk);
+      sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
+      s_fresh_done = sd.c.phase == PH_DONE;
+    }
+  } else if (threadIdx.x == 0) {
+    s_fresh_done = 0;
+    sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
+  }
+  __syncthreads();
+  copy_dyn(&sd, &q->dyn[par ^ 1]);
+  if (threadIdx.x == 0 && s_fresh_done && S->host_flag) {
+    __threadfence();
+    __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+constexpr int kCoreWords = (int)(sizeof(QPCore) / 4);
+static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
+
+// One workgroup per tile of every QP of the launch.
+template <typename CT, bool SPEC>
+__global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
+  __shared__ QPCore sc;
+  int tile;
+  QPDev *q = launch_qp(L, xcd_tile((int)blockIdx.x, (int)gridDim.x), &tile);
+  const QPStatic *S = &q->st;
+  const int par = L.parity;
+  const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
+  const bool own = SPEC && kk < S->n;
+  CGOperands<CT> P;
+  if (own) cg_prefetch<CT>(S, par, kk, P);
+  if (threadIdx.x < kCoreWords)
+    reinterpret_cast<uint32_t *>(&sc)[threadIdx.x] =
+        reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c)[threadIdx.x];
+  __syncthreads();
+  const int phase = sc.phase;
+  if (phase == PH_DONE) return;
+  const int mixed = S->mixed;
+  const int64_t k0 = (int64_t)tile * S->tile;
+  const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
+  double acc[kNP];
+  float accf[2] = {0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
+  if (SPEC && phase == PH_CG_ITER) {
+    CT gam = CT(0), del = CT(0);
+    if (own) cg_iter_prefetched<CT>(S, sc, par, kk, P, gam, del);
+    if (sizeof(CT) == 4) {
+      accf[0] = (float)gam;
+      accf[1] = (float)del;
+    } else {
+      acc[0] = (double)gam;
+      acc[1] = (double)del;
+    }
+  } else {
+    run_pass<CT>(S, sc, phase, par, k0, k1, acc, accf);
+  }
+  write_partial(tile_slots(q), par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
 }
 
 // Persistent form (batches of small QPs): one cooperative launch runs every
@@ -742,14 +1051,16 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
   if (threadIdx.x == 0) s_exit = 0;
   __syncthreads();
   int par = 0;
+  double *slots = tile_slots(q);
   for (uint32_t round = 1;; ++round) {
-    if (sd.pending) {
-      double R[kNP];
-      sum_partials(S->partials[par], S->ntiles, f32_slots(S->mixed, sd.phase), R);
-      if (threadIdx.x == 0) transition(S, sd, R);
+    if (sd.c.pending) {
+      double R[kNP], pf[kNP];
+      prefetch_slot(slots, par, pf);
+      sum_partials(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
+      if (threadIdx.x == 0) advance(S, sd, R, wall_clock64());
       __syncthreads();
     }
-    const int phase = sd.phase;
+    const int phase = sd.c.phase;
     if (phase == PH_DONE) break;
     for (int tile = lw; tile < S->ntiles; tile += nwg) {
       const int64_t k0 = (int64_t)tile * S->tile;
@@ -758,10 +1069,11 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
       float accf[2] = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-      run_pass<CT>(S, sd, phase, k0, k1, acc, accf);
-      write_partial(S->partials[par ^ 1], f32_slots(S->mixed, phase), tile, acc, accf);
+      run_pass<CT>(S, sd.c, phase, par, k0, k1, acc, accf);
+      write_partial(slots, par ^ 1, phase, f32_slots(S->mixed, phase), tile, acc, accf);
+      __syncthreads();
     }
-    if (threadIdx.x == 0) sd.pending = 1;
+    if (threadIdx.x == 0) sd.c.pending = 1;
     par ^= 1;
     if (nwg > 1) {
       __threadfence();  // publish this workgroup's vector and slot stores
@@ -784,15 +1096,15 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
     __syncthreads();
     if (s_exit) {
       if (threadIdx.x == 0) {
-        sd.status = GPCG_ERR_HANG;
-        sd.phase = PH_DONE;
+        sd.c.status = GPCG_ERR_HANG;
+        sd.c.phase = PH_DONE;
       }
       __syncthreads();
       break;
     }
   }
   if (lw == 0) {
-    if (threadIdx.x == 0) sd.pending = 0;
+    if (threadIdx.x == 0) sd.c.pending = 0;
     __syncthreads();
     copy_dyn(&sd, &q->dyn[0]);
     copy_dyn(&sd, &q->dyn[1]);
@@ -867,8 +1179,9 @@ __global__ __launch_bounds__(kBlock) void convert_f32_kernel(const double *__res
 // ------------------------------------------------------------ host launchers
 using namespace gpcg;
 
-void *gpcg_step_kernel_ptr(int mixed) {
-  return mixed ? (void *)&step_kernel<float> : (void *)&step_kernel<double>;
+void *gpcg_step_kernel_ptr(int mixed, int spec) {
+  if (spec) return mixed ? (void *)&step_kernel<float, true> : (void *)&step_kernel<double, true>;
+  return mixed ? (void *)&step_kernel<float, false> : (void *)&step_kernel<double, false>;
 }
 
 int gpcg_persistent_max_blocks(int mixed, int *blocks_per_cu) {
@@ -888,14 +1201,26 @@ int gpcg_launch_persistent(const PersistLaunch &P, int grid, int mixed, void *st
   return e == hipSuccess ? 0 : -1;
 }
 
-int gpcg_launch_step(const StepLaunch &L, int mixed, void *stream) {
+void *gpcg_transition_kernel_ptr() { return (void *)&transition_kernel; }
+
+void *gpcg_pass_kernel_ptr(int mixed, int spec) {
+  if (spec) return mixed ? (void *)&pass_kernel<float, true> : (void *)&pass_kernel<double, true>;
+  return mixed ? (void *)&pass_kernel<float, false> : (void *)&pass_kernel<double, false>;
+}
+
+int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
   if (L.total_tiles <= 0) return 0;
-  if (mixed)
-    hipLaunchKernelGGL(step_kernel<float>, dim3(L.total_tiles), dim3(kBlock), 0,
-                       (hipStream_t)stream, L);
-  else
-    hipLaunchKernelGGL(step_kernel<double>, dim3(L.total_tiles), dim3(kBlock), 0,
-                       (hipStream_t)stream, L);
+  const int tgrid = L.single ? 1 : L.nqp;
+  hipLaunchKernelGGL(transition_kernel, dim3(tgrid), dim3(kBlock), 0, (hipStream_t)stream, L);
+  hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_pass_kernel_ptr(mixed, spec)),
+                     dim3(L.total_tiles), dim3(kBlock), 0, (hipStream_t)stream, L);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int gpcg_launch_step(const StepLaunch &L, int mixed, int spec, void *stream) {
+  if (L.total_tiles <= 0) return 0;
+  hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_step_kernel_ptr(mixed, spec)),
+                     dim3(L.total_tiles), dim3(kBlock), 0, (hipStream_t)stream, L);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -95,24 +95,27 @@ int validate_opt(const gpcg_options *o) {
   if (o->chunk < 0 || o->chunk > 4096 || (o->chunk & 1))
     return fail(GPCG_ERR_ARG, "chunk must be even and at most 4096");
   if (o->max_stall < 1) return fail(GPCG_ERR_ARG, "max_stall must be >= 1");
+  if (o->form < GPCG_FORM_AUTO || o->form > GPCG_FORM_SPLIT)
+    return fail(GPCG_ERR_ARG, "unknown launch form");
   return GPCG_OK;
 }
 
-// Unknowns per workgroup and pass, chosen from the size alone so that a QP
-// reduces in the same order whether it is solved alone or inside a batch.
-// One unknown per thread while that keeps at most 1024 tiles (every
-// workgroup sums all tile slots of the previous pass), then more.
-int tuned_tile(int64_t n) {
-  const int64_t per = ((int64_t)1024 * kBlock);
-  const int64_t e = (n + per - 1) / per;
-  return (int)(kBlock * std::max<int64_t>(1, e));
-}
+// Unknowns per workgroup and pass: one per thread.  The same for every size
+// and every launch form, so a QP reduces in the same order alone, in a batch
+// or in the server.
+int tuned_tile(int64_t) { return kBlock; }
+
+// The fused form sums every tile slot of the previous pass in every
+// workgroup; beyond this many tiles the split form is cheaper.
+constexpr int kFusedMaxTiles = 1024;
 
 struct Layout {
-  size_t qp, part0, part1, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
+  size_t qp, slots, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
   size_t wx32, wy32, vals32, total;
   int tile, ntiles;
 };
+
+static_assert(kQPDevBytes % 256 == 0, "the slots follow the state at an aligned offset");
 
 Layout layout_for(const gpcg_operator *op, int precision, int tile_opt) {
   Layout L{};
@@ -128,8 +131,7 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt) {
     return at;
   };
   L.qp = take(sizeof(QPDev));
-  L.part0 = take(sizeof(double) * kNP * (size_t)L.ntiles);
-  L.part1 = take(sizeof(double) * kNP * (size_t)L.ntiles);
+  L.slots = take(tile_slot_bytes(L.ntiles));  // at L.qp + kQPDevBytes
   L.pgpart = take(sizeof(double) * 4 * 2048 + 64);
   L.x1 = take(8 * (size_t)n);
   L.g0 = take(8 * (size_t)n);
@@ -202,18 +204,19 @@ void put_options(QPStatic &s, const gpcg_options &o) {
 // The initial state of a solve (phase INIT, nothing pending).
 void initial_dyn(QPDyn &d) {
   std::memset(&d, 0, sizeof(d));
-  d.phase = PH_INIT;
-  d.ctx = CTX_INIT;
-  d.status = GPCG_OK;
-  d.gp_decmax = -INFINITY;
-  d.cg_decmax = -INFINITY;
+  d.c.phase = PH_INIT;
+  d.c.ctx = CTX_INIT;
+  d.c.status = GPCG_OK;
+  d.c.gp_decmax = -INFINITY;
+  d.c.cg_decmax = -INFINITY;
 }
 
 // Algorithmic HBM bytes of a finished solve: every array a pass touches is
 // counted once per pass (stencil neighbours are assumed reused on chip).
 // Passes that sweep only the free set (CG iterations) count the mask byte for
 // every unknown and the vector traffic for the free unknowns.
-double solve_bytes(const QPStatic &s, const QPDyn &d) {
+double solve_bytes(const QPStatic &s, const QPDyn &dy) {
+  const QPCore &d = dy.c;
   const bool mixed = s.mixed != 0;
   const double c = mixed ? 4.0 : 8.0;
   double coef64 = 0.0, coefc = 0.0;
@@ -225,20 +228,21 @@ double solve_bytes(const QPStatic &s, const QPDyn &d) {
     coefc = 4.0 + 5.0 * (mixed ? 8.0 : 12.0);
   }
   const double n = (double)s.n;
-  const double it = (double)d.pass_count[PH_CG_ITER];
+  const double it = (double)dy.pass_count[PH_CG_ITER];
   const double mean_m = it > 0 ? (double)d.cg_free_rows / it : 0.5 * n;
   double B = 0.0;
-  B += d.pass_count[PH_INIT] * n * (48.0 + coef64);      // x0, l, u, b in; x, g out
-  B += d.pass_count[PH_GP_ALPHA] * n * (32.0 + coef64);  // x, l, u, g
-  B += d.pass_count[PH_GP_TRIAL] * n * (56.0 + coef64);  // x, l, u, g, b in; x', g' out
-  B += d.pass_count[PH_CG_INIT] * (n * 33.0 + mean_m * (3 * c + coefc) + (n - mean_m) * 7 * c);
+  B += dy.pass_count[PH_INIT] * n * (48.0 + coef64);      // x0, l, u, b in; x, g out
+  B += dy.pass_count[PH_GP_ALPHA] * n * (32.0 + coef64);  // x, l, u, g
+  B += dy.pass_count[PH_GP_TRIAL] * n * (56.0 + coef64);  // x, l, u, g, b in; x', g' out
+  B += dy.pass_count[PH_CG_INIT] * (n * 33.0 + mean_m * (3 * c + coefc) + (n - mean_m) * 7 * c);
   B += (double)d.cg_free_rows * (10 * c + coefc) + it * n * 1.0;  // rho,u,s,p,w in+out; mask
-  B += d.pass_count[PH_PS_TRIAL] * (n * (57.0 + coef64) + mean_m * c);
+  B += dy.pass_count[PH_PS_TRIAL] * (n * (57.0 + coef64) + mean_m * c);
   return B;
 }
 
-void fill_stats(const QPStatic &s, const QPDyn &d, double tick_hz, gpcg_stats *st) {
+void fill_stats(const QPStatic &s, const QPDyn &dy, double tick_hz, gpcg_stats *st) {
   if (!st) return;
+  const QPCore &d = dy.c;
   std::memset(st, 0, sizeof(*st));
   st->status = d.status;
   st->outer_iters = d.outer_iters;
@@ -256,38 +260,53 @@ void fill_stats(const QPStatic &s, const QPDyn &d, double tick_hz, gpcg_stats *s
   st->n_upper = d.n_upper;
   st->n_free = s.n - d.n_lower - d.n_upper;
   st->passes = d.passes;
-  st->bytes = solve_bytes(s, d);
+  st->bytes = solve_bytes(s, dy);
   const double ms = 1e3 / tick_hz;
-  st->ms_cg = d.t_bucket[TB_CG] * ms;
-  st->ms_gp = d.t_bucket[TB_GP] * ms;
-  st->ms_search = d.t_bucket[TB_SEARCH] * ms;
-  st->ms_other = d.t_bucket[TB_OTHER] * ms;
+  st->ms_cg = dy.t_bucket[TB_CG] * ms;
+  st->ms_gp = dy.t_bucket[TB_GP] * ms;
+  st->ms_search = dy.t_bucket[TB_SEARCH] * ms;
+  st->ms_other = dy.t_bucket[TB_OTHER] * ms;
 }
 
-// A graph of `count` chained launches of the pass kernel with alternating
-// parity (count is even, so replays continue the parity sequence).
-int build_chain_graph(const StepLaunch &L, int mixed, int count, hipGraphExec_t *out) {
+// A graph of `count` chained steps with alternating parity (count is even, so
+// replays continue the parity sequence).  A fused step is one launch of the
+// pass kernel; a split step is the transition kernel then the data kernel.
+int build_chain_graph(const StepLaunch &L, int mixed, int spec, int split, int count,
+                      hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   HIP_OK(hipGraphCreate(&g, 0));
   hipGraphNode_t prev = nullptr;
-  for (int i = 0; i < count; ++i) {
+  auto add = [&](void *func, unsigned grid, const StepLaunch &arg0) -> int {
     hipKernelNodeParams p{};
-    p.func = gpcg_step_kernel_ptr(mixed);
-    p.gridDim = dim3((unsigned)L.total_tiles);
+    p.func = func;
+    p.gridDim = dim3(grid);
     p.blockDim = dim3(kBlock);
     p.sharedMemBytes = 0;
-    StepLaunch arg = L;
-    arg.parity = i & 1;
+    StepLaunch arg = arg0;
     void *args[] = {&arg};
     p.kernelParams = args;
     p.extra = nullptr;
     hipGraphNode_t node;
     hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
       return fail(GPCG_ERR_HIP, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
-    }
     prev = node;
+    return GPCG_OK;
+  };
+  for (int i = 0; i < count; ++i) {
+    StepLaunch arg = L;
+    arg.parity = i & 1;
+    int rc;
+    if (split) {
+      rc = add(gpcg_transition_kernel_ptr(), L.single ? 1u : (unsigned)L.nqp, arg);
+      if (!rc) rc = add(gpcg_pass_kernel_ptr(mixed, spec), (unsigned)L.total_tiles, arg);
+    } else {
+      rc = add(gpcg_step_kernel_ptr(mixed, spec), (unsigned)L.total_tiles, arg);
+    }
+    if (rc) {
+      (void)hipGraphDestroy(g);
+      return rc;
+    }
   }
   hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -296,17 +315,19 @@ int build_chain_graph(const StepLaunch &L, int mixed, int count, hipGraphExec_t 
   return GPCG_OK;
 }
 
-// Launches one chunk: the graph, or `chunk` plain launches of alternating
-// parity starting at 0.
-int launch_chunk(hipStream_t stream, StepLaunch L, int mixed, int chunk, hipGraphExec_t graph) {
+// Launches one chunk: the graph, or `chunk` plain steps of alternating parity
+// starting at 0.
+int launch_chunk(hipStream_t stream, StepLaunch L, int mixed, int spec, int split, int chunk,
+                 hipGraphExec_t graph) {
   if (graph) {
     HIP_OK(hipGraphLaunch(graph, stream));
     return GPCG_OK;
   }
   for (int i = 0; i < chunk; ++i) {
     L.parity = i & 1;
-    if (gpcg_launch_step(L, mixed, stream) != 0)
-      return fail(GPCG_ERR_HIP, "pass kernel launch failed");
+    const int rc = split ? gpcg_launch_split(L, mixed, spec, stream)
+                         : gpcg_launch_step(L, mixed, spec, stream);
+    if (rc != 0) return fail(GPCG_ERR_HIP, "pass kernel launch failed");
   }
   return GPCG_OK;
 }
@@ -314,17 +335,18 @@ int launch_chunk(hipStream_t stream, StepLaunch L, int mixed, int chunk, hipGrap
 // Replays chunks until `done()` holds.  Keeps one chunk queued behind the one
 // the host waits on, so the GPU does not idle while the host checks.
 template <class Done>
-int run_until(hipStream_t stream, const StepLaunch &L, int mixed, int chunk, hipGraphExec_t graph,
+int run_until(hipStream_t stream, const StepLaunch &L, int mixed, int spec, int split, int chunk,
+              hipGraphExec_t graph,
               hipEvent_t *ev, Done done, int64_t max_launches, int64_t *launches,
               int64_t *checks) {
-  int rc = launch_chunk(stream, L, mixed, chunk, graph);
+  int rc = launch_chunk(stream, L, mixed, spec, split, chunk, graph);
   if (rc) return rc;
   *launches += chunk;
   HIP_OK(hipEventRecord(ev[0], stream));
   for (int64_t i = 1;; ++i) {
     if (*launches >= max_launches)
       return fail(GPCG_ERR_HANG, "device did not finish within the launch budget");
-    rc = launch_chunk(stream, L, mixed, chunk, graph);
+    rc = launch_chunk(stream, L, mixed, spec, split, chunk, graph);
     if (rc) return rc;
     *launches += chunk;
     HIP_OK(hipEventRecord(ev[i & 1], stream));
@@ -346,6 +368,10 @@ int run_until(hipStream_t stream, const StepLaunch &L, int mixed, int chunk, hip
 
 int default_chunk(const gpcg_options &o) { return o.chunk > 0 ? o.chunk : 32; }
 
+// Whether a QP may run in the launch variant with speculative CG operand
+// loads (stencil operator, one unknown per thread).
+bool spec_ok(const QPStatic &s) { return s.tile == kBlock && s.op_kind != OPK_CSR; }
+
 }  // namespace
 
 // ------------------------------------------------------------------ handle
@@ -365,6 +391,7 @@ struct gpcg_handle_s {
   int graph_chunk = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
   double tick_hz;
+  int split;            // launch form of this handle's solves
 };
 
 namespace {
@@ -408,8 +435,6 @@ void fill_static(gpcg_handle_s *h) {
   q.pv = ws + L.p;
   q.wv = ws + L.w;
   q.mask = (uint8_t *)(ws + L.mask);
-  q.partials[0] = (double *)(ws + L.part0);
-  q.partials[1] = (double *)(ws + L.part1);
   q.host_flag = h->flag.dev;
   put_options(q, h->opt);
 }
@@ -436,7 +461,7 @@ int upload_solve(gpcg_handle_s *h, const double *b, const double *l, const doubl
 int finish_solve(gpcg_handle_s *h, int final_parity, double *g_out, hipStream_t stream) {
   HIP_OK(hipMemcpyAsync(h->stage, h->dqp, sizeof(QPDev), hipMemcpyDeviceToHost, stream));
   HIP_OK(hipStreamSynchronize(stream));
-  const QPDyn &d = h->stage->dyn[final_parity];
+  const QPCore &d = h->stage->dyn[final_parity].c;
   const QPStatic &s = h->stage->st;
   const size_t bytes = sizeof(double) * (size_t)s.n;
   if (d.cur == 1)
@@ -470,6 +495,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->chunk = 0;
   o->use_graph = 1;
   o->max_stall = 25;
+  o->form = GPCG_FORM_AUTO;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {
@@ -521,6 +547,8 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
     return cleanup(fail(GPCG_ERR_HIP, "hipHostMalloc of the staging state failed"));
   h->stage = (QPDev *)st;
   fill_static(h);
+  h->split = o.form == GPCG_FORM_SPLIT ||
+             (o.form == GPCG_FORM_AUTO && h->L.ntiles > kFusedMaxTiles);
   if (hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "hipEventCreate failed"));
@@ -569,20 +597,22 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   if (h->opt.use_graph && (!h->graph || h->graph_chunk != chunk)) {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
-    rc = build_chain_graph(SL, h->st.mixed, chunk, &h->graph);
+    rc = build_chain_graph(SL, h->st.mixed, spec_ok(h->st), h->split, chunk, &h->graph);
     if (rc) return rc;
     h->graph_chunk = chunk;
   }
   int64_t launches = 0, checks = 0;
   volatile int32_t *flag = h->flag.host;
-  rc = run_until(h->stream, SL, h->st.mixed, chunk, h->opt.use_graph ? h->graph : nullptr, h->ev,
+  rc = run_until(h->stream, SL, h->st.mixed, spec_ok(h->st), h->split, chunk,
+                 h->opt.use_graph ? h->graph : nullptr, h->ev,
                  [&] { return *flag != 0; }, (int64_t)1 << 26, &launches, &checks);
   if (rc) return rc;
   rc = finish_solve(h, (int)(launches & 1), g_out, h->stream);
   if (rc) return rc;
-  const QPDyn &d = h->stage->dyn[launches & 1];
+  const QPDyn &dy = h->stage->dyn[launches & 1];
+  const QPCore &d = dy.c;
   if (stats) {
-    fill_stats(h->stage->st, d, h->tick_hz, stats);
+    fill_stats(h->stage->st, dy, h->tick_hz, stats);
     stats->launches = launches;
     stats->host_checks = checks;
     stats->ms_total = (now_s() - t0) * 1e3;
@@ -838,8 +868,10 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       SL.prefix = b->prefix;
       SL.nqp = (int32_t)active.size();
       SL.total_tiles = total;
+      bool spec = true;
+      for (int i : active) spec = spec && spec_ok(b->hs[i]->st);
       hipGraphExec_t graph = nullptr;
-      int rc = build_chain_graph(SL, b->mixed, chunk, &graph);
+      int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
       if (rc) return rc;
       // run until at least a third of this launch's tiles belong to finished QPs
       auto enough = [&]() {
@@ -848,7 +880,7 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
           if (b->flags.host[i]) done_tiles += b->hs[i]->st.ntiles;
         return 3 * done_tiles >= total;
       };
-      rc = run_until(b->stream, SL, b->mixed, chunk, graph, b->ev, enough, (int64_t)1 << 26,
+      rc = run_until(b->stream, SL, b->mixed, spec, 1, chunk, graph, b->ev, enough, (int64_t)1 << 26,
                      &launches, &checks);
       (void)hipGraphExecDestroy(graph);
       if (rc) return rc;
@@ -865,10 +897,10 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     gpcg_handle h = b->hs[i];
     int rc = finish_solve(h, final_parity, probs[i].g_out, b->stream);
     if (rc) return rc;
-    const QPDyn &d = h->stage->dyn[final_parity];
-    if (d.status < 0 && first_err == GPCG_OK) first_err = d.status;
+    const QPDyn &dy = h->stage->dyn[final_parity];
+    if (dy.c.status < 0 && first_err == GPCG_OK) first_err = dy.c.status;
     if (stats) {
-      fill_stats(h->stage->st, d, h->tick_hz, &stats[i]);
+      fill_stats(h->stage->st, dy, h->tick_hz, &stats[i]);
       stats[i].launches = launches;
       stats[i].host_checks = checks;
       stats[i].ms_total = ms;
@@ -1040,8 +1072,6 @@ int srv_admit(gpcg_server_s *s, int slot_id, const SrvPending &p, size_t off) {
   S.pv = base + L.p;
   S.wv = base + L.w;
   S.mask = (uint8_t *)(base + L.mask);
-  S.partials[0] = (double *)(base + L.part0);
-  S.partials[1] = (double *)(base + L.part1);
   S.host_flag = s->flags.dev + slot_id;
   put_options(S, s->solve_opt);
   initial_dyn(q.dyn[0]);
@@ -1079,7 +1109,7 @@ int srv_retire(gpcg_server_s *s) {
     SrvSlot &sl = s->slots[i];
     const ReqLayout R = req_layout(&sl.req.op, s->opt.precision);
     char *base = s->arena + sl.off;
-    const QPDyn &d = s->stage[i].dyn[par];
+    const QPCore &d = s->stage[i].dyn[par].c;
     if (sl.req.x_out)
       HIP_OK(hipMemcpyAsync(sl.req.x_out, base + (d.cur ? R.L.x1 : R.x0),
                             8 * (size_t)op_n(&sl.req.op), hipMemcpyDeviceToDevice, s->stream));
@@ -1088,11 +1118,11 @@ int srv_retire(gpcg_server_s *s) {
   const double t = now_s();
   for (int i : fin) {
     SrvSlot &sl = s->slots[i];
-    const QPDyn &d = s->stage[i].dyn[par];
+    const QPDyn &dy = s->stage[i].dyn[par];
     gpcg_completion c{};
     c.tag = sl.req.tag;
-    fill_stats(s->stage[i].st, d, s->tick_hz, &c.stats);
-    c.status = d.status;
+    fill_stats(s->stage[i].st, dy, s->tick_hz, &c.stats);
+    c.status = dy.c.status;
     c.t_submit = sl.t_submit;
     c.t_admit = sl.t_admit;
     c.t_done = t;
@@ -1202,9 +1232,11 @@ int gpcg_server_step(gpcg_server s, int *active) {
     auto **qp = (QPDev **)s->stage_tables;
     auto *pre = (int32_t *)(s->stage_tables + align_up(sizeof(void *) * s->slots.size()));
     int cnt = 0;
+    bool spec = true;
     pre[0] = 0;
     for (int i = 0; i < (int)s->slots.size(); ++i) {
       if (!s->slots[i].used) continue;
+      spec = spec && req_layout(&s->slots[i].req.op, s->opt.precision).L.tile == kBlock;
       const ReqLayout R = req_layout(&s->slots[i].req.op, s->opt.precision);
       qp[cnt] = (QPDev *)(s->arena + s->slots[i].off + R.L.qp);
       pre[cnt + 1] = pre[cnt] + s->slots[i].ntiles;
@@ -1219,7 +1251,7 @@ int gpcg_server_step(gpcg_server s, int *active) {
     SL.total_tiles = pre[cnt];
     for (int k = 0; k < s->opt.quantum; ++k) {
       SL.parity = (int)(s->launches & 1);
-      if (gpcg_launch_step(SL, s->opt.precision == GPCG_PREC_MIXED, s->stream) != 0)
+      if (gpcg_launch_split(SL, s->opt.precision == GPCG_PREC_MIXED, spec, s->stream) != 0)
         return fail(GPCG_ERR_HIP, "pass kernel launch failed");
       s->launches += 1;
     }

@@ -145,6 +145,29 @@ def test_deterministic_and_graph_invariant():
         assert s1[k] == s2[k] == s3[k], k
 
 
+@pytest.mark.parametrize("case", ["c0", "c0_csr", "c1s", "ragged_mixed", "ragged_csr_mixed"])
+def test_fused_and_split_forms_agree_bitwise(case):
+    """The two launch forms use the same tiles and summation orders."""
+    import paper_cs_0101018_amd as gpcg
+    inst, kind, prec = {
+        "c0": (instances.config0(0), None, gpcg.GPCG_PREC_FP64),
+        "c0_csr": (instances.config0(0), "csr", gpcg.GPCG_PREC_FP64),
+        "c1s": (instances.varcoef(96, 3), None, gpcg.GPCG_PREC_FP64),
+        "ragged_mixed": (instances.obstacle(77, 5), None, gpcg.GPCG_PREC_MIXED),
+        "ragged_csr_mixed": (instances.obstacle(77, 5), "csr", gpcg.GPCG_PREC_MIXED),
+    }[case]
+    res = [G.solve(inst, kind, precision=prec, form=f)
+           for f in (gpcg.GPCG_FORM_FUSED, gpcg.GPCG_FORM_SPLIT)]
+    res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT,
+                       use_graph=0, chunk=10))
+    (x1, g1, s1) = res[0]
+    assert s1["status"] == gpcg.GPCG_OK
+    for x, g, st in res[1:]:
+        assert np.array_equal(x, x1) and np.array_equal(g, g1)
+        for k in ("outer_iters", "gp_iters", "cg_iters", "backtracks", "passes"):
+            assert st[k] == s1[k], k
+
+
 def test_start_outside_box_is_projected():
     inst = instances.config0(4)
     inst.x0 = inst.x0.copy()
