@@ -9,14 +9,22 @@ HBM before the timed region; each step restores x0 on the device.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--no-cpu-baseline] [--extras] [--copy-calib]
+    python bench.py --counters FETCH_DIR WRITE_DIR   (summarise two rocprofv3
+                    --pmc runs, FETCH_SIZE then WRITE_SIZE, as text)
 
-Prints one JSON line.
+Prints one JSON line.  `roofline.traffic` comes from the committed counter
+summary of the workload's kernel when its kernel-source digest matches the
+sources being run, else null.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,27 +37,121 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E datasheet peak
 
 WORKLOADS = {
     # name: (instance factory, options, description)
-    "varcoef256_fp64": ("config1", dict(), "GPCG FP64, -div(c grad u) 256x256 (n=65,536), "
+    "varcoef256_fp64": ("varcoef256", dict(), "GPCG FP64, -div(c grad u) 256x256 (n=65,536), "
                         "c=(1+0.1 cos 2 pi s)^3, l=0, u=inf, tol 1e-8 rel"),
-    "varcoef256_mixed": ("config1", dict(precision=1), "GPCG mixed FP32-CG, varcoef 256x256"),
-    "obstacle50_fp64": ("config0", dict(), "GPCG FP64, obstacle 50x50"),
-    "obstacle1024_fp64": ("config2_1024", dict(), "GPCG FP64, obstacle 1024x1024"),
-    "obstacle1024_mixed": ("config2_1024", dict(precision=1), "GPCG mixed, obstacle 1024x1024"),
-    "obstacle1600_fp64": ("config2_1600", dict(), "GPCG FP64, obstacle 1600x1600"),
-    "obstacle1600_mixed": ("config2_1600", dict(precision=1), "GPCG mixed, obstacle 1600x1600"),
+    "varcoef256_mixed": ("varcoef256", dict(precision=1), "GPCG mixed FP32-CG, varcoef 256x256"),
+    "obstacle50_fp64": ("obstacle50", dict(), "GPCG FP64, obstacle 50x50"),
+    "obstacle1024_fp64": ("obstacle_ub_1024", dict(), "GPCG FP64, obstacle 1024x1024"),
+    "obstacle1024_mixed": ("obstacle_ub_1024", dict(precision=1), "GPCG mixed, obstacle 1024x1024"),
+    "obstacle1600_fp64": ("obstacle_ub_1600", dict(), "GPCG FP64, obstacle 1600x1600"),
+    "obstacle1600_mixed": ("obstacle_ub_1600", dict(precision=1), "GPCG mixed, obstacle 1600x1600"),
 }
 BATCH_WORKLOADS = ("batch512_fp64", "batch512_mixed")
 SERVE_WORKLOADS = ("serve4096",)
 
 
+KERNEL_SOURCES = ("paper_cs_0101018_amd/csrc/gpcg_kernels.hip",
+                  "paper_cs_0101018_amd/csrc/gpcg_internal.h")
+COPY_CALIB_BYTES = 256 << 20
+
+
+def kernel_digest():
+    """sha256 over the device sources: counters taken on other code are stale."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(d):
+    files = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    for fn in files:
+        with open(fn, newline="") as f:
+            yield from csv.DictReader(f)
+
+
+def _per_dispatch_kib(d, counter):
+    """{kernel name: [KiB of each dispatch]} for one counter."""
+    acc = {}
+    for r in _counter_rows(d):
+        if r.get("Counter_Name") != counter:
+            continue
+        name = r.get("Kernel_Name", "?")
+        key = r.get("Dispatch_Id", r.get("Correlation_Id"))
+        acc.setdefault(name, {})
+        acc[name][key] = acc[name].get(key, 0.0) + float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in acc.items()}
+
+
+def counters_summary(fetch_dir, write_dir):
+    """Text summary of a FETCH_SIZE run and a WRITE_SIZE run: mean KiB per
+    dispatch by kernel, and the scale factor that maps the counter of the
+    256 MiB calibration copy (the largest copy dispatch: 256 MiB read, 256 MiB
+    written) onto the bytes it is known to move."""
+    fetch = _per_dispatch_kib(fetch_dir, "FETCH_SIZE")
+    write = _per_dispatch_kib(write_dir, "WRITE_SIZE")
+    known_kib = COPY_CALIB_BYTES / 1024.0
+
+    def calib(tab):
+        cands = [(max(v), k) for k, v in tab.items() if "copy" in k.lower() and v]
+        if not cands or max(cands)[0] <= 0.0:
+            return None, None, None
+        val, name = max(cands)
+        return known_kib / val, name, val
+
+    cf, cname, cfv = calib(fetch)
+    cw, _, cwv = calib(write)
+    mean = lambda v: sum(v) / len(v) if v else float("nan")
+    lines = [f"kernel_source_sha256: {kernel_digest()}",
+             f"copy_calibration_kernel: {cname}",
+             f"copy_calibration_fetch_kib: {cfv}",
+             f"copy_calibration_write_kib: {cwv}",
+             f"calib_factor_fetch: {cf}",
+             f"calib_factor_write: {cw}",
+             "",
+             f"{'kernel':90s} {'dispatches':>10s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s}"]
+    for k in sorted(set(fetch) | set(write), key=lambda k: -len(fetch.get(k, []))):
+        f, w = fetch.get(k, []), write.get(k, [])
+        lines.append(f"{k[:90]:90s} {max(len(f), len(w)):10d} {mean(f):12.1f} {mean(w):12.1f}")
+    return "\n".join(lines)
+
+
+def traffic_from_profile(workload, kernel_substr):
+    """HBM bytes per launch of the kernel from the committed counter summary
+    (scaled by the copy calibration), or None when absent or stale."""
+    fn = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(fn):
+        return None
+    txt = open(fn).read()
+    kv = dict(re.findall(r"^(\w+): (\S+)$", txt, re.M))
+    if kv.get("kernel_source_sha256") != kernel_digest():
+        return None
+    try:
+        cf, cw = float(kv["calib_factor_fetch"]), float(kv["calib_factor_write"])
+    except (KeyError, ValueError):
+        return None
+    for line in txt.splitlines():
+        parts = line.split()
+        if len(parts) >= 4 and kernel_substr in line:
+            try:
+                f, w = float(parts[-2]), float(parts[-1])
+            except ValueError:
+                continue
+            return (f * cf + w * cw) * 1024.0
+    return None
+
+
 def make_instance(key):
     import instances
-    if key == "config0":
-        return instances.config0(0)
-    if key == "config1":
-        return instances.config1(0)
-    if key.startswith("config2_"):
-        return instances.config2(int(key.split("_")[1]), 0)
+    if key == "obstacle50":
+        return instances.obstacle50(0)
+    if key == "varcoef256":
+        return instances.varcoef256(0)
+    if key.startswith("obstacle_ub_"):
+        return instances.obstacle_ub(int(key.split("_")[-1]), 0)
     raise KeyError(key)
 
 
@@ -76,37 +178,40 @@ def cpu_baseline(inst, budget_s=12.0):
                        f"(single-threaded C, -O2 -ffp-contract=off)")
 
 
-def spmv_extras(gpcg, torch, dev):
-    """SpMV bandwidth of the building-block kernel on the large grids, warm and
-    with the 256 MB last-level cache flushed before each launch."""
+def spmv_extras(gpcg, torch, dev, reps=40):
+    """Bandwidth of the SpMV building block y = M o (A v) on the large grids:
+    `reps` back-to-back launches timed with HIP events on the launch stream.
+    Warm: one (v, y, mask) set, resident in the 256 MB last-level cache where
+    it fits.  Cold: the launches cycle through enough sets (> 1 GiB) that every
+    launch reads from HBM."""
     out = {}
-    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
     for N in (1024, 1600):
         for prec in (0, 1):
             op = gpcg.Operator.stencil_const(N, N, float((N + 1) ** 2))
             s = gpcg.Solver(op, device=dev, precision=prec)
             dt = torch.float32 if prec else torch.float64
-            v = torch.randn(N * N, dtype=torch.float64, device=dev).to(dt)
-            y = torch.empty_like(v)
-            mask = torch.ones(N * N, dtype=torch.uint8, device=dev)
-            per = 2 * v.element_size() + 1
+            per = 2 * (4 if prec else 8) + 1
+            set_bytes = per * N * N
             for cold in (False, True):
-                times = []
-                for it in range(12):
-                    if cold:
-                        flush.fill_(it & 0xFF)
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    s.spmv(v, y, mask)
-                    e1.record()
-                    torch.cuda.synchronize()
-                    times.append(e0.elapsed_time(e1))
-                t = float(np.median(times[2:])) * 1e-3
+                nsets = max(1, -(-(1 << 30) // set_bytes)) if cold else 1
+                sets = [(torch.randn(N * N, dtype=torch.float64, device=dev).to(dt),
+                         torch.empty(N * N, dtype=dt, device=dev),
+                         torch.ones(N * N, dtype=torch.uint8, device=dev)) for _ in range(nsets)]
+                for i in range(min(nsets, 4)):
+                    s.spmv(*sets[i])
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for i in range(reps):
+                    s.spmv(*sets[i % nsets])
+                e1.record()
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
                 key = f"spmv_const{N}_{'fp32' if prec else 'fp64'}_{'cold' if cold else 'warm'}"
-                out[key] = dict(GBs=round(per * N * N / t / 1e9, 1), us=round(t * 1e6, 2),
-                                bytes_per_var=per)
+                out[key] = dict(GBs=round(set_bytes / t / 1e9, 1), us=round(t * 1e6, 2),
+                                bytes_per_var=per, frac=round(set_bytes / t / 1e9 / HBM_PEAK_GBS, 3))
+                del sets
             s.close()
-    del flush
     return out
 
 
@@ -126,10 +231,11 @@ def bench_batch(args, gpcg, torch, dev):
     stepped graph chunks) against 512 sequential plain FP64 solves."""
     import instances
     mixed = args.workload.endswith("mixed")
-    insts = instances.config3(0)
+    insts = instances.batch512(0)
     data = [_dev_instance(i, gpcg, torch, dev) for i in insts]
     mode = gpcg.GPCG_BATCH_PERSISTENT if args.batch_mode == "persistent" else gpcg.GPCG_BATCH_STEPPED
-    solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed)) for d in data]
+    fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
+    solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed), free_set=fs) for d in data]
     batch = gpcg.Batch(solvers, device=dev)
     xs = [torch.empty_like(d[4]) for d in data]
     probs = [(d[1], d[2], d[3], x) for d, x in zip(data, xs)]
@@ -167,7 +273,7 @@ def bench_batch(args, gpcg, torch, dev):
         "value": round(len(insts) / wall, 2), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32cg" if mixed else "f64", "data": "synthetic (config-3 generator, seed 0)",
+        "dtype": "f64+f32cg" if mixed else "f64", "data": "synthetic (512 obstacle / variable-coefficient QPs, sides log-uniform in [32, 384], seed 0)",
         "config": {"workload": args.workload, "qps": len(insts), "unknowns": n_tot,
                    "batch_mode": args.batch_mode},
         "sequential_fp64": {"solves_per_s": round(len(insts) / seq_wall, 2),
@@ -184,11 +290,11 @@ def bench_serve(args, gpcg, torch, dev):
     one-at-a-time loop (FIFO, service times measured on the same GPU)."""
     import instances
     count = args.requests
-    arr = instances.config4_trace(0, count)
+    arr = instances.serve_trace(0, count)
     log(f"serve: generating {count} requests")
     reqs = []
     for i in range(count):
-        inst = instances.config4_request(0, i, count)
+        inst = instances.serve_request(0, i, count)
         reqs.append((inst.n,) + _dev_instance(inst, gpcg, torch, dev))
     torch.cuda.synchronize()
     arena = 8 << 30
@@ -209,6 +315,8 @@ def bench_serve(args, gpcg, torch, dev):
         active = srv.step()
         for c in srv.poll(1024):
             done[c["tag"]] = c
+            if len(done) % 512 == 0:
+                log(f"serve: {len(done)}/{count} done")
         if active == 0 and nxt < count:
             time.sleep(max(0.0, min(0.002, arr[nxt] - (time.perf_counter() - t0))))
     wall = time.perf_counter() - t0
@@ -229,6 +337,8 @@ def bench_serve(args, gpcg, torch, dev):
         torch.cuda.synchronize()
         service[i] = time.perf_counter() - ts
         s_.close()
+        if (i + 1) % 512 == 0:
+            log(f"serve: baseline {i + 1}/{count} solves")
     finish = np.zeros(count)
     tcur = 0.0
     for i in range(count):
@@ -240,7 +350,7 @@ def bench_serve(args, gpcg, torch, dev):
         "value": round(count / wall, 2), "unit": "solves/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": round(wall * 1e3, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32cg", "data": "synthetic (config-4 generator and trace, seed 0)",
+        "dtype": "f64+f32cg", "data": "synthetic (Poisson trace, 200 req/s; sides log-uniform in [32, 512], seed 0)",
         "config": {"workload": "serve4096", "requests": count, "rate_hz": 200,
                    "max_slots": 512, "quantum": 32},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
@@ -265,14 +375,22 @@ def main():
     ap.add_argument("--requests", type=int, default=4096, help="serving: trace length")
     ap.add_argument("--form", default="auto", choices=["auto", "fused", "split"],
                     help="launch form of single-QP workloads")
+    ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
+                    help="free set of the reduced CG: byte mask or compacted list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time SpMV on 1024^2/1600^2")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration)")
+    ap.add_argument("--counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.counters:
+        print(counters_summary(*args.counters))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the QPs would shard by grid strips or by QP; not built). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -291,7 +409,7 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     if args.copy_calib:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        a = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
@@ -305,7 +423,8 @@ def main():
         op = gpcg.Operator.stencil_const(N, N, inst.w)
     form = {"auto": gpcg.GPCG_FORM_AUTO, "fused": gpcg.GPCG_FORM_FUSED,
             "split": gpcg.GPCG_FORM_SPLIT}[args.form]
-    solver = gpcg.Solver(op, device=dev, form=form, **opts)
+    fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
+    solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
 
@@ -337,6 +456,15 @@ def main():
     bytes_per_launch = alg_bytes / launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
     solves_per_s = args.steps / wall
+    ntiles = -(-inst.n // 256)
+    fused = args.form == "fused" or (args.form == "auto" and ntiles <= 1024)
+    if fused:
+        kname, ksub = "gpcg::step_kernel (one fused GPCG pass per launch)", "step_kernel"
+    else:
+        kname = ("gpcg::pass_kernel (data kernel of the split form; the time per launch "
+                 "is that of one transition + data kernel pair)")
+        ksub = "pass_kernel"
+    traffic = traffic_from_profile(args.workload, ksub)
 
     res = {
         "metric": "GPCG solves/sec (proj-grad tol 1e-8 rel)",
@@ -352,16 +480,17 @@ def main():
         "dtype": "f64" if not opts.get("precision") else "f64+f32cg",
         "data": "synthetic (seeded instance generator, seed 0)",
         "config": {"workload": args.workload, "description": desc, "n": inst.n,
+                   "free_set": args.free_set, "form": args.form,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "gpcg::step_kernel (one fused GPCG pass per launch)",
+            "kernel": kname,
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
+            "traffic": None if traffic is None else round(traffic, 1),
             "bytes_per_launch": round(bytes_per_launch, 1),
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "launches_per_solve": launches / args.steps,

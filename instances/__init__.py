@@ -153,7 +153,7 @@ def varcoef_weights(N: int, eps: float = 0.1):
     return wx, wy
 
 
-# --------------------------------------------------------------- configs
+# ------------------------------------------------------- benchmark workloads
 
 def _obstacle_lower(N, rng, amplitude=0.3):
     s, t, _ = grid_coords(N)
@@ -201,17 +201,17 @@ def varcoef(N: int, seed: int = 0, *, eps: float = 0.1, name: Optional[str] = No
                     meta=dict(seed=seed, eps=eps))
 
 
-def config0(seed: int = 0) -> Instance:
+def obstacle50(seed: int = 0) -> Instance:
     """Plain FP64 obstacle QP on a 50 x 50 grid (n = 2,500)."""
     return obstacle(50, seed, name="obstacle50")
 
 
-def config1(seed: int = 0) -> Instance:
+def varcoef256(seed: int = 0) -> Instance:
     """Plain FP64 variable-coefficient QP on a 256 x 256 grid (n = 65,536)."""
     return varcoef(256, seed, name="varcoef256")
 
 
-def config2(N: int = 1024, seed: int = 0) -> Instance:
+def obstacle_ub(N: int = 1024, seed: int = 0) -> Instance:
     """Obstacle QP at scale (N = 1024 or 1600) with a random upper bound."""
     return obstacle(N, seed, u_random=True, name=f"obstacle{N}_ub")
 
@@ -240,19 +240,19 @@ def _mixed_member(ss: np.random.SeedSequence, nmin: int, nmax: int, idx: int) ->
     return inst
 
 
-def config3(seed: int = 0, count: int = 512, nmin: int = 32, nmax: int = 384):
+def batch512(seed: int = 0, count: int = 512, nmin: int = 32, nmax: int = 384):
     """512 independent QPs of uneven size (sides log-uniform in [32, 384])."""
     children = np.random.SeedSequence(seed).spawn(count)
     return [_mixed_member(c, nmin, nmax, i) for i, c in enumerate(children)]
 
 
-def config4_trace(seed: int = 0, count: int = 4096, rate_hz: float = 200.0):
+def serve_trace(seed: int = 0, count: int = 4096, rate_hz: float = 200.0):
     """Poisson arrival times (seconds) for the serving workload."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 4]))
     return np.cumsum(rng.exponential(1.0 / rate_hz, count))
 
 
-def config4_request(seed: int, index: int, count: int = 4096,
+def serve_request(seed: int, index: int, count: int = 4096,
                     nmin: int = 32, nmax: int = 512) -> Instance:
     """Request ``index`` of the serving workload (sides log-uniform in [32, 512])."""
     children = np.random.SeedSequence(seed).spawn(count)

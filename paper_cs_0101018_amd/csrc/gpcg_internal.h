@@ -28,6 +28,7 @@ enum Phase : int32_t {
   PH_CG_INIT,     // free mask, rho = -g on F, u = A rho, w = 0
   PH_CG_ITER,     // one single-reduction CG iteration on the free set
   PH_PS_TRIAL,    // x' = P[x + alpha w] and g' = Ax' - b: decrease and face of x'
+  PH_CG_LIST,     // list form: compact the free mask into an ascending index list
   PH_DONE,
   PH_COUNT
 };
@@ -58,6 +59,7 @@ struct QPStatic {
   void *rho[2], *uq[2], *sq[2];  // CG residual, A*residual, A*direction (FP64/FP32)
   void *pv, *wv;                 // CG direction and iterate
   uint8_t *mask;                 // free set of the current CG phase
+  int32_t *list;                 // list form: free indices in ascending order (else null)
   int32_t *host_flag;            // device view of a mapped host word, or null
   double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
 };

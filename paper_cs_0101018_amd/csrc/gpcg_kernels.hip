@@ -257,6 +257,7 @@ __device__ __forceinline__ int nslots(int phase) {
   switch (phase) {
     case PH_GP_ALPHA: case PH_CG_ITER: return 2;
     case PH_CG_INIT: return 3;
+    case PH_CG_LIST: return 1;
     default: return kNP;
   }
 }
@@ -364,10 +365,13 @@ __device__ __forceinline__ void face_acc(double x, double l, double u, double g,
   acc[4] = __fma_rn(x, g - b, acc[4]);
 }
 
+// One pass over the unknowns [k0, k1) of a tile (the list entries [k0, k1)
+// for a CG iteration of the list form).  `slots` are the QP's tile slots: the
+// list pass reads the free counts the set-up pass left at parity lpar.
 template <typename CT>
-__device__ void run_pass(const QPStatic *__restrict__ S, const QPCore &d, int phase, int lpar,
-                         int64_t k0,
-                         int64_t k1, double (&acc)[kNP], float (&accf)[2]) {
+__device__ void run_pass(const QPStatic *__restrict__ S, const double *__restrict__ slots,
+                         const QPCore &d, int phase, int lpar, int64_t k0, int64_t k1,
+                         double (&acc)[kNP], float (&accf)[2]) {
   const double *__restrict__ l = S->l;
   const double *__restrict__ u = S->u;
   const double *__restrict__ b = S->b;
@@ -433,11 +437,13 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const QPCore &d, int ph
     case PH_CG_INIT: {
       const OpView<CT> A = op_view<CT>(S);
       uint8_t *__restrict__ mask = S->mask;
-      // the first CG iteration runs in the next launch, which reads parity lpar ^ 1
-      CT *__restrict__ r0 = (CT *)S->rho[lpar ^ 1];
-      CT *__restrict__ u0 = (CT *)S->uq[lpar ^ 1];
-      CT *__restrict__ r1 = (CT *)S->rho[lpar];
-      CT *__restrict__ u1 = (CT *)S->uq[lpar];
+      // the first CG iteration runs in the next launch, which reads parity
+      // lpar ^ 1 (in the list form, two launches later: parity lpar)
+      const int fp = S->list ? lpar : lpar ^ 1;
+      CT *__restrict__ r0 = (CT *)S->rho[fp];
+      CT *__restrict__ u0 = (CT *)S->uq[fp];
+      CT *__restrict__ r1 = (CT *)S->rho[fp ^ 1];
+      CT *__restrict__ u1 = (CT *)S->uq[fp ^ 1];
       CT *__restrict__ s0 = (CT *)S->sq[0];
       CT *__restrict__ s1 = (CT *)S->sq[1];
       CT *__restrict__ p = (CT *)S->pv;
@@ -476,6 +482,29 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const QPCore &d, int ph
         }
       }
     } break;
+    case PH_CG_LIST: {
+      // offset of this tile in the list = free rows of the tiles before it
+      // (slot 2 of the set-up pass, exact integers in FP64)
+      const int tile = (int)(k0 / kBlock);
+      double before[1] = {0.0};
+      for (int t = (int)threadIdx.x; t < tile; t += kBlock)
+        before[0] += slots[((int64_t)t * 2 + lpar) * kNP + 2];
+      block_sum<double, 1>(before);
+      __shared__ int64_t s_base;
+      __shared__ int s_wave[kBlock / 64];
+      if (threadIdx.x == 0) s_base = (int64_t)before[0];
+      const int64_t k = k0 + threadIdx.x;
+      const bool fr = k < k1 && S->mask[k] != 0;
+      const uint64_t bal = __ballot(fr);
+      const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+      const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wave[wv] = __popcll(bal);
+      __syncthreads();
+      int off = 0;
+      for (int i = 0; i < wv; ++i) off += s_wave[i];
+      if (fr) S->list[s_base + off + rank] = (int32_t)k;
+      __syncthreads();
+    } break;
     case PH_CG_ITER: {
       const OpView<CT> A = op_view<CT>(S);
       const uint8_t *__restrict__ mask = S->mask;
@@ -494,8 +523,13 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const QPCore &d, int ph
       auto snew = [&](int64_t j) { return first ? uo[j] : fmaT<CT>(be, so[j], uo[j]); };
       auto rnew = [&](int64_t j) { return fmaT<CT>(-al, snew(j), ro[j]); };
       CT gam = CT(0), del = CT(0);
-      for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
-        if (!mask[k]) continue;  // the CG vectors vanish on the active set
+      const int32_t *__restrict__ list = S->list;
+      // list form: entries [k0, k1) of the free list; mask form: rows [k0, k1)
+      const int64_t e1 = list ? (k1 < d.m_free ? k1 : d.m_free) : k1;
+      for (int64_t e = k0 + threadIdx.x; e < e1; e += st) {
+        int64_t k = e;
+        if (list) k = list[e];
+        else if (!mask[k]) continue;  // the CG vectors vanish on the active set
         const CT rk = ro[k];
         const CT sk = snew(k);
         const CT r1 = fmaT<CT>(-al, sk, rk);
@@ -550,7 +584,7 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const QPCore &d, int ph
 
 __device__ __forceinline__ int time_bucket(int phase) {
   switch (phase) {
-    case PH_CG_INIT: case PH_CG_ITER: return TB_CG;
+    case PH_CG_INIT: case PH_CG_LIST: case PH_CG_ITER: return TB_CG;
     case PH_GP_ALPHA: case PH_GP_TRIAL: return TB_GP;
     case PH_PS_TRIAL: return TB_SEARCH;
     default: return TB_OTHER;
@@ -667,9 +701,12 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
       else {
         d.cg_alpha = d.gamma / R[1];
         d.cg_beta = 0.0;
-        d.phase = PH_CG_ITER;
+        d.phase = S->list ? PH_CG_LIST : PH_CG_ITER;
       }
     } break;
+    case PH_CG_LIST:
+      d.phase = PH_CG_ITER;
+      break;
     case PH_CG_ITER: {
       d.cg_j += 1;
       d.cg_iters += 1;
@@ -910,7 +947,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
         acc[1] = (double)del;
       }
     } else {
-      run_pass<CT>(S, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
     }
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     __syncthreads();
@@ -1018,7 +1055,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
       acc[1] = (double)del;
     }
   } else {
-    run_pass<CT>(S, sc, phase, par, k0, k1, acc, accf);
+    run_pass<CT>(S, tile_slots(q), sc, phase, par, k0, k1, acc, accf);
   }
   write_partial(tile_slots(q), par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
 }
@@ -1069,7 +1106,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
       float accf[2] = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-      run_pass<CT>(S, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
       write_partial(slots, par ^ 1, phase, f32_slots(S->mixed, phase), tile, acc, accf);
       __syncthreads();
     }

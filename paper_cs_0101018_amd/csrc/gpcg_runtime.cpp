@@ -88,6 +88,8 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "iteration caps must be positive");
   if (o->precision != GPCG_PREC_FP64 && o->precision != GPCG_PREC_MIXED)
     return fail(GPCG_ERR_ARG, "unknown precision");
+  if (o->free_set == GPCG_FREESET_LIST && o->tile != 0 && o->tile != kBlock)
+    return fail(GPCG_ERR_ARG, "the list free set needs 256-unknown tiles");
   if (o->free_set != GPCG_FREESET_MASK && o->free_set != GPCG_FREESET_LIST)
     return fail(GPCG_ERR_ARG, "unknown free-set mode");
   if (o->tile < 0 || o->tile % kBlock != 0 || o->tile > (1 << 16))
@@ -111,13 +113,13 @@ constexpr int kFusedMaxTiles = 1024;
 
 struct Layout {
   size_t qp, slots, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
-  size_t wx32, wy32, vals32, total;
+  size_t wx32, wy32, vals32, list, total;
   int tile, ntiles;
 };
 
 static_assert(kQPDevBytes % 256 == 0, "the slots follow the state at an aligned offset");
 
-Layout layout_for(const gpcg_operator *op, int precision, int tile_opt) {
+Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free_set) {
   Layout L{};
   const int64_t n = op_n(op);
   const bool mixed = precision == GPCG_PREC_MIXED;
@@ -151,6 +153,7 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt) {
     L.wy32 = take(4 * (size_t)(op->ny + 1) * op->nx);
   }
   if (mixed && op->kind == GPCG_OP_CSR) L.vals32 = take(4 * (size_t)op->nnz);
+  L.list = free_set == GPCG_FREESET_LIST ? take(4 * (size_t)n) : 0;
   L.total = off;
   return L;
 }
@@ -235,7 +238,14 @@ double solve_bytes(const QPStatic &s, const QPDyn &dy) {
   B += dy.pass_count[PH_GP_ALPHA] * n * (32.0 + coef64);  // x, l, u, g
   B += dy.pass_count[PH_GP_TRIAL] * n * (56.0 + coef64);  // x, l, u, g, b in; x', g' out
   B += dy.pass_count[PH_CG_INIT] * (n * 33.0 + mean_m * (3 * c + coefc) + (n - mean_m) * 7 * c);
-  B += (double)d.cg_free_rows * (10 * c + coefc) + it * n * 1.0;  // rho,u,s,p,w in+out; mask
+  if (s.list) {
+    // list form: the index of each free row instead of the mask of every row;
+    // the list pass reads the mask and writes the list
+    B += (double)d.cg_free_rows * (10 * c + coefc + 4.0);
+    B += dy.pass_count[PH_CG_LIST] * (n * 1.0 + mean_m * 4.0);
+  } else {
+    B += (double)d.cg_free_rows * (10 * c + coefc) + it * n * 1.0;  // rho,u,s,p,w in+out; mask
+  }
   B += dy.pass_count[PH_PS_TRIAL] * (n * (57.0 + coef64) + mean_m * c);
   return B;
 }
@@ -370,7 +380,9 @@ int default_chunk(const gpcg_options &o) { return o.chunk > 0 ? o.chunk : 32; }
 
 // Whether a QP may run in the launch variant with speculative CG operand
 // loads (stencil operator, one unknown per thread).
-bool spec_ok(const QPStatic &s) { return s.tile == kBlock && s.op_kind != OPK_CSR; }
+bool spec_ok(const QPStatic &s) {
+  return s.tile == kBlock && s.op_kind != OPK_CSR && s.list == nullptr;
+}
 
 }  // namespace
 
@@ -435,6 +447,7 @@ void fill_static(gpcg_handle_s *h) {
   q.pv = ws + L.p;
   q.wv = ws + L.w;
   q.mask = (uint8_t *)(ws + L.mask);
+  q.list = L.list ? (int32_t *)(ws + L.list) : nullptr;
   q.host_flag = h->flag.dev;
   put_options(q, h->opt);
 }
@@ -507,7 +520,7 @@ int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
-  *bytes = layout_for(op, o.precision, o.tile).total;
+  *bytes = layout_for(op, o.precision, o.tile, o.free_set).total;
   return GPCG_OK;
 }
 
@@ -522,7 +535,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
-  Layout L = layout_for(op, o.precision, o.tile);
+  Layout L = layout_for(op, o.precision, o.tile, o.free_set);
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
     return fail(GPCG_ERR_WORKSPACE, "workspace missing or not 256-byte aligned");
   if (ws_bytes < L.total)
@@ -563,8 +576,13 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   if (L.vals32 &&
       gpcg_launch_convert_f32(op->vals, (float *)(h->ws + L.vals32), op->nnz, stream))
     return cleanup(fail(GPCG_ERR_HIP, "FP32 value conversion failed"));
-  if (hipStreamSynchronize(h->stream) != hipSuccess)
-    return cleanup(fail(GPCG_ERR_HIP, "stream synchronize failed in create"));
+  // the operator part of the device state is valid from here on (the
+  // building-block kernels read it; solves rewrite only the vector pointers)
+  h->stage->st = h->st;
+  if (hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return cleanup(fail(GPCG_ERR_HIP, "state upload failed in create"));
   *out = h;
   return GPCG_OK;
 }
@@ -623,11 +641,7 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
 
 int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
-  // the kernel reads the operator from the device state: refresh it
-  HIP_OK(hipStreamSynchronize(h->stream));
-  h->stage->st = h->st;
-  HIP_OK(hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
-                        h->stream));
+  // the kernel reads the operator from the device state uploaded at create
   if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 0, h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
@@ -636,10 +650,6 @@ int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
 int gpcg_spmv_f32(gpcg_handle h, const float *v, float *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
   if (!h->st.mixed) return fail(GPCG_ERR_ARG, "handle was not created with GPCG_PREC_MIXED");
-  HIP_OK(hipStreamSynchronize(h->stream));
-  h->stage->st = h->st;
-  HIP_OK(hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
-                        h->stream));
   if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 1, h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
@@ -926,7 +936,7 @@ struct ReqLayout {
 
 ReqLayout req_layout(const gpcg_operator *op, int precision) {
   ReqLayout R{};
-  R.L = layout_for(op, precision, 0);
+  R.L = layout_for(op, precision, 0, GPCG_FREESET_MASK);
   const int64_t n = op_n(op);
   size_t off = R.L.total;
   auto take = [&](size_t bytes) {

@@ -73,7 +73,7 @@ def pin_projected_gradient_cases(o):
 
 def pin_gradient_matches_sparse_library(o):
     """g = A x - b against SciPy's CSR product."""
-    inst = instances.config1(seed=3)
+    inst = instances.varcoef256(seed=3)
     csr = inst.csr()
     A = exact.csr_matrix(csr)
     x = np.random.default_rng(2).standard_normal(inst.n)
@@ -86,7 +86,7 @@ def pin_gradient_matches_sparse_library(o):
 
 def pin_alpha0_minimises_along_projected_gradient(o):
     """alpha_0 of eq. (bqpls) is the minimiser of q(y - alpha P grad q(y))."""
-    inst = instances.config0(seed=5)
+    inst = instances.obstacle50(seed=5)
     csr = inst.csr()
     A = exact.csr_matrix(csr)
     y = inst.x0
@@ -257,7 +257,7 @@ def pin_manufactured(o):
 def pin_matches_independent_exact_solver(o):
     """The obstacle problem (n = 2500) against primal-dual active set + sparse
     direct solves, a method sharing nothing with GPCG."""
-    inst = instances.config0(seed=1)
+    inst = instances.obstacle50(seed=1)
     csr = inst.csr()
     x, g, st = o.solve_instance(inst, **TIGHT)
     xs, info = exact.polish(csr, inst.b, inst.l, inst.u, None)
@@ -270,7 +270,7 @@ def pin_invariants(o):
     """q decreases at every projected search (sufficient decrease), the active
     set does not shrink across a CG step + projected search (the CG direction
     is zero on A(x_k)), and the answer is feasible."""
-    inst = instances.config0(seed=2)
+    inst = instances.obstacle50(seed=2)
     x, g, st = o.solve_instance(inst, trace_cap=1000)
     tq = st["trace_q"]
     assert len(tq) == st["outer_iters"] >= 2

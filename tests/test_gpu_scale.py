@@ -24,7 +24,7 @@ _XSTAR = {}
 
 def xstar(N):
     if N not in _XSTAR:
-        inst = instances.config2(N, 0)
+        inst = instances.obstacle_ub(N, 0)
         xo, _, _ = oracle.default().solve_instance(inst, tol_rel=1e-10)
         xs, info = exact.polish(inst.csr(), inst.b, inst.l, inst.u, xo)
         assert info["converged"]
@@ -62,7 +62,7 @@ def test_obstacle1024_matches_exact_solution():
 @pytest.mark.timeout(600)
 def test_obstacle1600_properties():
     import paper_cs_0101018_amd as gpcg
-    inst = instances.config2(1600, 0)
+    inst = instances.obstacle_ub(1600, 0)
     res = {}
     for prec in (gpcg.GPCG_PREC_FP64, gpcg.GPCG_PREC_MIXED):
         x, g, st = G.solve(inst, precision=prec)

@@ -48,10 +48,10 @@ def cpu_projected_gradient_norm(inst, x):
 
 
 CASES = [
-    ("c0", lambda: instances.config0(0), None),
-    ("c0_csr", lambda: instances.config0(0), "csr"),
-    ("c1", lambda: instances.config1(0), None),
-    ("c1_csr", lambda: instances.config1(0), "csr"),
+    ("c0", lambda: instances.obstacle50(0), None),
+    ("c0_csr", lambda: instances.obstacle50(0), "csr"),
+    ("c1", lambda: instances.varcoef256(0), None),
+    ("c1_csr", lambda: instances.varcoef256(0), "csr"),
     ("obst_ragged", lambda: instances.obstacle(77, 3, amplitude=0.45, u_random=True), None),
 ]
 
@@ -74,8 +74,8 @@ def test_fp64_matches_oracle(name, make, kind):
     assert np.allclose(g, A @ x - inst.b, rtol=0, atol=1e-9 * np.abs(inst.b).max() + 1e-12)
 
 
-@pytest.mark.parametrize("name,make", [("c0", lambda: instances.config0(0)),
-                                       ("c1", lambda: instances.config1(0))])
+@pytest.mark.parametrize("name,make", [("c0", lambda: instances.obstacle50(0)),
+                                       ("c1", lambda: instances.varcoef256(0))])
 def test_metric_tolerance_holds_on_cpu(name, make):
     """At the metric tolerance (1e-8 relative) the answer satisfies the
     termination test when its projected gradient is recomputed on the CPU."""
@@ -90,7 +90,7 @@ def test_metric_tolerance_holds_on_cpu(name, make):
 
 def test_mixed_precision_matches_oracle():
     import paper_cs_0101018_amd as gpcg
-    inst = instances.config1(0)
+    inst = instances.varcoef256(0)
     xs, gs, _ = reference("c1", inst)
     x, g, st = G.solve(inst, precision=gpcg.GPCG_PREC_MIXED, tol_rel=1e-10)
     err = G.rel_inf(x, xs)
@@ -135,7 +135,7 @@ def test_unconstrained_matches_direct_solve():
 
 
 def test_deterministic_and_graph_invariant():
-    inst = instances.config0(2)
+    inst = instances.obstacle50(2)
     x1, g1, s1 = G.solve(inst)
     x2, g2, s2 = G.solve(inst)
     x3, g3, s3 = G.solve(inst, use_graph=0, chunk=6)
@@ -150,8 +150,8 @@ def test_fused_and_split_forms_agree_bitwise(case):
     """The two launch forms use the same tiles and summation orders."""
     import paper_cs_0101018_amd as gpcg
     inst, kind, prec = {
-        "c0": (instances.config0(0), None, gpcg.GPCG_PREC_FP64),
-        "c0_csr": (instances.config0(0), "csr", gpcg.GPCG_PREC_FP64),
+        "c0": (instances.obstacle50(0), None, gpcg.GPCG_PREC_FP64),
+        "c0_csr": (instances.obstacle50(0), "csr", gpcg.GPCG_PREC_FP64),
         "c1s": (instances.varcoef(96, 3), None, gpcg.GPCG_PREC_FP64),
         "ragged_mixed": (instances.obstacle(77, 5), None, gpcg.GPCG_PREC_MIXED),
         "ragged_csr_mixed": (instances.obstacle(77, 5), "csr", gpcg.GPCG_PREC_MIXED),
@@ -169,12 +169,12 @@ def test_fused_and_split_forms_agree_bitwise(case):
 
 
 def test_start_outside_box_is_projected():
-    inst = instances.config0(4)
+    inst = instances.obstacle50(4)
     inst.x0 = inst.x0.copy()
     inst.x0[::5] = 3.0
     x, g, st = G.solve(inst, tol_rel=TIGHT)
     assert st["x0_projected"] == 1 and st["status"] == 0
-    xs, gs, _ = reference("c0s4", instances.config0(4))
+    xs, gs, _ = reference("c0s4", instances.obstacle50(4))
     assert G.rel_inf(x, xs) <= 1e-8
 
 

@@ -26,7 +26,7 @@ def test_paper_constants(ora):
 
 
 def test_start_outside_box_is_projected(ora):
-    inst = instances.config0(seed=4)
+    inst = instances.obstacle50(seed=4)
     x_ref, _, st_ref = ora.solve_instance(inst)
     x0 = inst.x0.copy()
     x0[::7] = 5.0  # above u = 0.25
@@ -54,7 +54,7 @@ def test_errors(ora):
 
 
 def test_iteration_caps(ora):
-    inst = instances.config0(seed=0)
+    inst = instances.obstacle50(seed=0)
     st = ora.solve_instance(inst, max_outer=1)[2]
     assert st["status"] == oracle.MAXIT and st["outer_iters"] == 1
     st = ora.solve_instance(inst, max_cg=1)[2]
@@ -65,7 +65,7 @@ def test_free_fraction_matches_stated_sanity(ora):
     """Sanity only (parity unpinned): the variable-coefficient instance ends
     with about two thirds of its variables free, the same regime as the
     paper's eps = 0.1 journal bearing (about 68% free, Section 5)."""
-    inst = instances.config1()
+    inst = instances.varcoef256()
     x, g, st = ora.solve_instance(inst)
     frac = st["n_free"] / inst.n
     assert 0.55 < frac < 0.75
