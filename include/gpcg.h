@@ -116,6 +116,9 @@ typedef struct {
                           has at most 1024 tiles of 256 unknowns, else split),
                           GPCG_FORM_FUSED or GPCG_FORM_SPLIT; the answer is
                           bitwise the same in every form                     */
+  int32_t tiles_per_wg; /* split form: consecutive 256-unknown tiles per data
+                          workgroup, 1..64; 0 = 1.  The answer does not
+                          depend on it                                        */
 } gpcg_options;
 
 #define GPCG_FORM_AUTO 0
@@ -215,8 +218,9 @@ typedef struct gpcg_batch_s *gpcg_batch;
 #define GPCG_BATCH_PERSISTENT 1 /* one cooperative launch; each QP advances on its
                                    own workgroups with a per-QP barrier            */
 
-/* Device workspace for a batch of `count` handles (tables of the launch). */
-int gpcg_batch_workspace_bytes(int count, size_t *bytes);
+/* Device workspace for a batch of the `count` handles (tables of the launch:
+ * QP pointers and one work item per tile of every QP). */
+int gpcg_batch_workspace_bytes(int count, const gpcg_handle *handles, size_t *bytes);
 
 /* Groups `count` handles (created with the same precision) into a batch.
  * The handles must outlive the batch. */

@@ -51,7 +51,8 @@ class gpcg_options(C.Structure):
                 ("max_outer", C.c_int32), ("max_gp", C.c_int32), ("max_backtrack", C.c_int32),
                 ("max_cg", C.c_int32), ("precision", C.c_int32), ("free_set", C.c_int32),
                 ("tile", C.c_int32), ("chunk", C.c_int32), ("use_graph", C.c_int32),
-                ("max_stall", C.c_int32), ("form", C.c_int32)]
+                ("max_stall", C.c_int32), ("form", C.c_int32),
+                ("tiles_per_wg", C.c_int32)]
 
 
 class gpcg_stats(C.Structure):
@@ -101,7 +102,7 @@ _SIGS = {
     "gpcg_spmv_f32": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gpcg_projected_gradient": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _P(C.c_double),
                                           _P(_i64), _P(_i64), _P(_i64)]),
-    "gpcg_batch_workspace_bytes": (C.c_int, [C.c_int, _P(_sz)]),
+    "gpcg_batch_workspace_bytes": (C.c_int, [C.c_int, C.c_void_p, _P(_sz)]),
     "gpcg_batch_create": (C.c_int, [C.c_int, _P(_vp), _vp, _sz, _vp, _P(_vp)]),
     "gpcg_batch_solve": (C.c_int, [_vp, _P(gpcg_problem), C.c_int, _P(gpcg_stats)]),
     "gpcg_batch_destroy": (C.c_int, [_vp]),
@@ -260,9 +261,10 @@ class Batch:
         self.solvers = list(solvers)
         cnt = len(self.solvers)
         nbytes = C.c_size_t()
-        check(_lib.gpcg_batch_workspace_bytes(cnt, C.byref(nbytes)), "gpcg_batch_workspace_bytes")
-        self._ws, ptr = _workspace(nbytes.value, device)
         arr = (C.c_void_p * cnt)(*[s.handle.value for s in self.solvers])
+        check(_lib.gpcg_batch_workspace_bytes(cnt, arr, C.byref(nbytes)),
+              "gpcg_batch_workspace_bytes")
+        self._ws, ptr = _workspace(nbytes.value, device)
         h = C.c_void_p()
         check(_lib.gpcg_batch_create(cnt, arr, ptr, nbytes.value, _stream_ptr(stream),
                                      C.byref(h)), "gpcg_batch_create")

@@ -108,13 +108,22 @@ __host__ __device__ inline size_t tile_slot_bytes(int ntiles) {
   return sizeof(double) * 2 * kNP * (size_t)(ntiles > kBlock ? ntiles : kBlock);
 }
 
+// Work of one data-kernel workgroup in a launch over several QPs: the tiles
+// tile0 .. tile0 + ntile - 1 of QP q.
+struct WgItem {
+  QPDev *q;
+  int32_t tile0, ntile;
+};
+
 struct StepLaunch {
   QPDev *single;           // one QP: its state (tables unused)
-  QPDev *const *qps;       // several QPs: device array of nqp pointers
-  const int32_t *prefix;   // device array, nqp+1 tile offsets
+  QPDev *const *qps;       // several QPs: device array of nqp pointers (transition kernel)
+  const WgItem *items;     // several QPs: device array of data_grid work items
   int32_t nqp;
-  int32_t total_tiles;
+  int32_t total_tiles;     // one QP: its tile count (grid of the fused kernel)
   int32_t parity;          // this launch reads dyn/partials[parity]
+  int32_t tiles_per_wg;    // one QP, split form: consecutive tiles per data workgroup
+  int32_t data_grid;       // split form: workgroups of the data kernel
   int32_t pad;
 };
 
@@ -138,7 +147,7 @@ void *gpcg_transition_kernel_ptr();
 void *gpcg_pass_kernel_ptr(int mixed, int spec);
 int gpcg_launch_split(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
 int gpcg_launch_spmv(const gpcg::QPDev *dqp, int64_t n, const void *v, void *y,
-                     const uint8_t *mask, int f32, void *stream);
+                     const uint8_t *mask, int f32, int vec_nx, void *stream);
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
                       const double *g, double *pg, double *part, double *out4, void *stream);
 int gpcg_launch_convert_f32(const double *src, float *dst, int64_t count, void *stream);

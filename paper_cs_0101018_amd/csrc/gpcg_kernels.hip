@@ -885,22 +885,9 @@ template <typename CT, bool SPEC>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ int s_fresh_done;
-  const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  QPDev *q;
-  int tile;
-  if (L.single) {
-    q = L.single;
-    tile = t;
-  } else {
-    int lo = 0, hi = L.nqp;
-    while (hi - lo > 1) {
-      const int m = (lo + hi) >> 1;
-      if (L.prefix[m] <= t) lo = m;
-      else hi = m;
-    }
-    q = L.qps[lo];
-    tile = t - L.prefix[lo];
-  }
+  // the fused form runs one QP (L.single); workgroup = tile
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  QPDev *q = L.single;
   const QPStatic *S = &q->st;
   const int par = L.parity;
   double *slots = tile_slots(q);
@@ -968,21 +955,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
 // dyn[p] and slots[p] and writes dyn[p ^ 1]; the data kernel reads dyn[p ^ 1]
 // and writes slots[p ^ 1]; CG buffers alternate with p as in the fused form.
 
-__device__ __forceinline__ QPDev *launch_qp(const StepLaunch &L, int t, int *tile) {
-  if (L.single) {
-    *tile = t;
-    return L.single;
-  }
-  int lo = 0, hi = L.nqp;
-  while (hi - lo > 1) {
-    const int m = (lo + hi) >> 1;
-    if (L.prefix[m] <= t) lo = m;
-    else hi = m;
-  }
-  *tile = t - L.prefix[lo];
-  return L.qps[lo];
-}
-
 // One workgroup per QP of the launch (L.single: grid 1; else grid nqp, QP b).
 __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
@@ -1019,16 +991,28 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
 constexpr int kCoreWords = (int)(sizeof(QPCore) / 4);
 static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 
-// One workgroup per tile of every QP of the launch.
+// One workgroup per work item: a run of consecutive tiles of one QP (one QP:
+// tiles_per_wg tiles per workgroup; several QPs: the item table).
 template <typename CT, bool SPEC>
 __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
-  int tile;
-  QPDev *q = launch_qp(L, xcd_tile((int)blockIdx.x, (int)gridDim.x), &tile);
+  const int wg = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  QPDev *q;
+  int t0, nt;
+  if (L.single) {
+    q = L.single;
+    t0 = wg * L.tiles_per_wg;
+    nt = L.tiles_per_wg;  // clipped to the QP's tiles below
+  } else {
+    const WgItem it = L.items[wg];
+    q = it.q;
+    t0 = it.tile0;
+    nt = it.ntile;
+  }
   const QPStatic *S = &q->st;
   const int par = L.parity;
-  const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
-  const bool own = SPEC && kk < S->n;
+  int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
+  bool own = SPEC && kk < S->n;
   CGOperands<CT> P;
   if (own) cg_prefetch<CT>(S, par, kk, P);
   if (threadIdx.x < kCoreWords)
@@ -1037,27 +1021,37 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __syncthreads();
   const int phase = sc.phase;
   if (phase == PH_DONE) return;
-  const int mixed = S->mixed;
-  const int64_t k0 = (int64_t)tile * S->tile;
-  const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
-  double acc[kNP];
-  float accf[2] = {0.0f, 0.0f};
+  const int mixed = S->mixed, ntiles = S->ntiles;
+  double *slots = tile_slots(q);
+  const int t1 = t0 + nt < ntiles ? t0 + nt : ntiles;
+  for (int tile = t0; tile < t1; ++tile) {
+    const int64_t k0 = (int64_t)tile * S->tile;
+    const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
+    double acc[kNP];
+    float accf[2] = {0.0f, 0.0f};
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-  if (SPEC && phase == PH_CG_ITER) {
-    CT gam = CT(0), del = CT(0);
-    if (own) cg_iter_prefetched<CT>(S, sc, par, kk, P, gam, del);
-    if (sizeof(CT) == 4) {
-      accf[0] = (float)gam;
-      accf[1] = (float)del;
+    for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
+    if (SPEC && phase == PH_CG_ITER) {
+      if (tile != t0) {
+        kk = k0 + threadIdx.x;
+        own = kk < S->n;
+        if (own) cg_prefetch<CT>(S, par, kk, P);
+      }
+      CT gam = CT(0), del = CT(0);
+      if (own) cg_iter_prefetched<CT>(S, sc, par, kk, P, gam, del);
+      if (sizeof(CT) == 4) {
+        accf[0] = (float)gam;
+        accf[1] = (float)del;
+      } else {
+        acc[0] = (double)gam;
+        acc[1] = (double)del;
+      }
     } else {
-      acc[0] = (double)gam;
-      acc[1] = (double)del;
+      run_pass<CT>(S, slots, sc, phase, par, k0, k1, acc, accf);
     }
-  } else {
-    run_pass<CT>(S, tile_slots(q), sc, phase, par, k0, k1, acc, accf);
+    write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
+    if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
   }
-  write_partial(tile_slots(q), par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
 }
 
 // Persistent form (batches of small QPs): one cooperative launch runs every
@@ -1171,6 +1165,75 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(const QPDev *q, const T *_
   }
 }
 
+// Vector-load variant for stencil operators with nx % V == 0: thread t owns
+// the V consecutive unknowns k = V t .. V t + V - 1 of one grid row, loads
+// them, the rows above and below and the mask with one V-wide access each,
+// and evaluates every unknown with the expression of apply_row (bitwise the
+// same result as spmv_kernel).
+template <typename T, int V>
+struct VecOf;
+template <> struct VecOf<double, 2> { using type = double2; };
+template <> struct VecOf<float, 4> { using type = float4; };
+template <int V> struct MaskOf;
+template <> struct MaskOf<2> { using type = uint16_t; };
+template <> struct MaskOf<4> { using type = uint32_t; };
+
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void spmv_stencil_kernel(const QPDev *q,
+                                                              const T *__restrict__ v,
+                                                              T *__restrict__ y,
+                                                              const uint8_t *__restrict__ mask) {
+  using VT = typename VecOf<T, V>::type;
+  using MT = typename MaskOf<V>::type;
+  const OpView<T> A = op_view<T>(&q->st);
+  const int64_t n = q->st.n;
+  const int64_t t = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * kBlock + threadIdx.x;
+  const int64_t k = t * V;
+  if (k >= n) return;
+  const int32_t nx = A.nx;
+  const int32_t j = (int32_t)(((uint64_t)k * A.magic) >> A.shift);
+  const int32_t i = (int32_t)(k - (int64_t)j * nx);
+  T c[V], s[V], nn[V], wv = T(0), ev = T(0);
+  *reinterpret_cast<VT *>(c) = *reinterpret_cast<const VT *>(v + k);
+  if (j > 0) *reinterpret_cast<VT *>(s) = *reinterpret_cast<const VT *>(v + k - nx);
+  else
+    for (int e = 0; e < V; ++e) s[e] = T(0);
+  if (j < A.ny - 1) *reinterpret_cast<VT *>(nn) = *reinterpret_cast<const VT *>(v + k + nx);
+  else
+    for (int e = 0; e < V; ++e) nn[e] = T(0);
+  if (i > 0) wv = v[k - 1];
+  if (i + V < nx) ev = v[k + V];
+  MT mbits = ~MT(0);
+  if (mask) mbits = *reinterpret_cast<const MT *>(mask + k);
+  T out[V];
+  if (A.kind == OPK_CONST) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const T vW = e == 0 ? wv : c[e - 1];
+      const T vE = e == V - 1 ? ev : c[e + 1];
+      out[e] = A.w * ((c[e] - vW) + (c[e] - vE) + ((c[e] - s[e]) + (c[e] - nn[e])));
+    }
+  } else {
+    const int64_t ex = (int64_t)j * (nx + 1) + i;
+    T wx[V + 1], wS[V], wN[V];
+#pragma unroll
+    for (int e = 0; e <= V; ++e) wx[e] = A.wx[ex + e];
+    *reinterpret_cast<VT *>(wS) = *reinterpret_cast<const VT *>(A.wy + k);
+    *reinterpret_cast<VT *>(wN) = *reinterpret_cast<const VT *>(A.wy + k + nx);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const T vW = e == 0 ? wv : c[e - 1];
+      const T vE = e == V - 1 ? ev : c[e + 1];
+      out[e] = (wx[e] * (c[e] - vW) + wx[e + 1] * (c[e] - vE)) +
+               (wS[e] * (c[e] - s[e]) + wN[e] * (c[e] - nn[e]));
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e)
+    if (((mbits >> (8 * e)) & 0xFF) == 0) out[e] = T(0);
+  *reinterpret_cast<VT *>(y + k) = *reinterpret_cast<const VT *>(out);
+}
+
 __global__ __launch_bounds__(kBlock) void pgrad_kernel(int64_t n, const double *__restrict__ x,
                                                        const double *__restrict__ l,
                                                        const double *__restrict__ u,
@@ -1246,16 +1309,16 @@ void *gpcg_pass_kernel_ptr(int mixed, int spec) {
 }
 
 int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
-  if (L.total_tiles <= 0) return 0;
+  if (L.data_grid < 1 || (!L.single && (!L.qps || !L.items || L.nqp < 1))) return -1;
   const int tgrid = L.single ? 1 : L.nqp;
   hipLaunchKernelGGL(transition_kernel, dim3(tgrid), dim3(kBlock), 0, (hipStream_t)stream, L);
   hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_pass_kernel_ptr(mixed, spec)),
-                     dim3(L.total_tiles), dim3(kBlock), 0, (hipStream_t)stream, L);
+                     dim3(L.data_grid), dim3(kBlock), 0, (hipStream_t)stream, L);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int gpcg_launch_step(const StepLaunch &L, int mixed, int spec, void *stream) {
-  if (L.total_tiles <= 0) return 0;
+  if (!L.single || L.total_tiles <= 0) return -1;
   hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_step_kernel_ptr(mixed, spec)),
                      dim3(L.total_tiles), dim3(kBlock), 0, (hipStream_t)stream, L);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1269,7 +1332,24 @@ static int grid_for(int64_t n) {
 }
 
 int gpcg_launch_spmv(const QPDev *dqp, int64_t n, const void *v, void *y, const uint8_t *mask,
-                     int f32, void *stream) {
+                     int f32, int vec_nx, void *stream) {
+  // vec_nx: the grid width of a stencil operator (0 for CSR); the V-wide
+  // kernel needs whole vectors per grid row and aligned arrays
+  const int V = f32 ? 4 : 2;
+  const bool aligned = ((uintptr_t)v % (V * (f32 ? 4 : 8))) == 0 &&
+                       ((uintptr_t)y % (V * (f32 ? 4 : 8))) == 0 &&
+                       (!mask || ((uintptr_t)mask % V) == 0);
+  if (vec_nx > 0 && vec_nx % V == 0 && aligned) {
+    const int64_t groups = n / V;
+    const int grid = (int)((groups + kBlock - 1) / kBlock);
+    if (f32)
+      hipLaunchKernelGGL((spmv_stencil_kernel<float, 4>), dim3(grid), dim3(kBlock), 0,
+                         (hipStream_t)stream, dqp, (const float *)v, (float *)y, mask);
+    else
+      hipLaunchKernelGGL((spmv_stencil_kernel<double, 2>), dim3(grid), dim3(kBlock), 0,
+                         (hipStream_t)stream, dqp, (const double *)v, (double *)y, mask);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   const int grid = grid_for(n);
   if (f32)
     hipLaunchKernelGGL(spmv_kernel<float>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, dqp,

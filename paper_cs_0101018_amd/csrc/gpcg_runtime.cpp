@@ -99,6 +99,8 @@ int validate_opt(const gpcg_options *o) {
   if (o->max_stall < 1) return fail(GPCG_ERR_ARG, "max_stall must be >= 1");
   if (o->form < GPCG_FORM_AUTO || o->form > GPCG_FORM_SPLIT)
     return fail(GPCG_ERR_ARG, "unknown launch form");
+  if (o->tiles_per_wg < 0 || o->tiles_per_wg > 64)
+    return fail(GPCG_ERR_ARG, "tiles_per_wg must be in [0, 64]");
   return GPCG_OK;
 }
 
@@ -309,7 +311,7 @@ int build_chain_graph(const StepLaunch &L, int mixed, int spec, int split, int c
     int rc;
     if (split) {
       rc = add(gpcg_transition_kernel_ptr(), L.single ? 1u : (unsigned)L.nqp, arg);
-      if (!rc) rc = add(gpcg_pass_kernel_ptr(mixed, spec), (unsigned)L.total_tiles, arg);
+      if (!rc) rc = add(gpcg_pass_kernel_ptr(mixed, spec), (unsigned)L.data_grid, arg);
     } else {
       rc = add(gpcg_step_kernel_ptr(mixed, spec), (unsigned)L.total_tiles, arg);
     }
@@ -404,6 +406,7 @@ struct gpcg_handle_s {
   hipEvent_t ev[2] = {nullptr, nullptr};
   double tick_hz;
   int split;            // launch form of this handle's solves
+  int tiles_per_wg;     // split form: consecutive tiles per data workgroup
 };
 
 namespace {
@@ -509,6 +512,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->use_graph = 1;
   o->max_stall = 25;
   o->form = GPCG_FORM_AUTO;
+  o->tiles_per_wg = 0;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {
@@ -562,6 +566,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   fill_static(h);
   h->split = o.form == GPCG_FORM_SPLIT ||
              (o.form == GPCG_FORM_AUTO && h->L.ntiles > kFusedMaxTiles);
+  h->tiles_per_wg = o.tiles_per_wg > 0 ? o.tiles_per_wg : 1;
   if (hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "hipEventCreate failed"));
@@ -611,6 +616,8 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   SL.single = h->dqp;
   SL.nqp = 1;
   SL.total_tiles = h->L.ntiles;
+  SL.tiles_per_wg = h->tiles_per_wg;
+  SL.data_grid = (h->L.ntiles + h->tiles_per_wg - 1) / h->tiles_per_wg;
   const int chunk = default_chunk(h->opt);
   if (h->opt.use_graph && (!h->graph || h->graph_chunk != chunk)) {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
@@ -639,10 +646,19 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   return d.status;
 }
 
+// Grid width for the vector-load SpMV kernel, or 0 to use the scalar one
+// (CSR, or edge weights not aligned to the vector width).
+static int spmv_vec_nx(const gpcg_handle_s *h, int f32) {
+  if (h->st.op_kind == OPK_CSR) return 0;
+  const void *wy = f32 ? (const void *)h->st.wy32 : (const void *)h->st.wy;
+  if (h->st.op_kind == OPK_VAR && ((uintptr_t)wy % 16) != 0) return 0;
+  return h->st.nx;
+}
+
 int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
   // the kernel reads the operator from the device state uploaded at create
-  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 0, h->stream))
+  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 0, spmv_vec_nx(h, 0), h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
 }
@@ -650,7 +666,7 @@ int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
 int gpcg_spmv_f32(gpcg_handle h, const float *v, float *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
   if (!h->st.mixed) return fail(GPCG_ERR_ARG, "handle was not created with GPCG_PREC_MIXED");
-  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 1, h->stream))
+  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 1, spmv_vec_nx(h, 1), h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
 }
@@ -702,8 +718,29 @@ const char *gpcg_build_info(void) {
 
 namespace {
 
-size_t tables_bytes(int count) {
+// Launch tables of a batch or the server: QP pointers, tile prefix sums (the
+// persistent form's workgroup offsets) and the work items of the data kernel.
+size_t tables_bytes(int count, size_t items) {
+  return align_up(sizeof(void *) * (size_t)count) + align_up(sizeof(int32_t) * (count + 1)) +
+         align_up(sizeof(WgItem) * items);
+}
+
+size_t items_offset(int count) {
   return align_up(sizeof(void *) * (size_t)count) + align_up(sizeof(int32_t) * (count + 1));
+}
+
+// Work items of a split data kernel over the QPs qp[0..cnt): runs of at most
+// T consecutive tiles, QP by QP.  Returns the number of items.
+int fill_items(WgItem *out, QPDev *const *qp, const int32_t *ntiles, int cnt, int T) {
+  int m = 0;
+  for (int a = 0; a < cnt; ++a)
+    for (int t = 0; t < ntiles[a]; t += T) {
+      out[m].q = qp[a];
+      out[m].tile0 = t;
+      out[m].ntile = std::min(T, ntiles[a] - t);
+      ++m;
+    }
+  return m;
 }
 
 // Workgroup slots per QP for the persistent form: proportional to the QP's
@@ -752,6 +789,7 @@ struct gpcg_batch_s {
   size_t ws_bytes;
   QPDev **qptrs;       // device
   int32_t *prefix;     // device
+  WgItem *items;       // device
   size_t tbytes;
   char *stage;         // pinned copy of the tables
   PinnedWords flags;   // one DONE word per QP
@@ -761,9 +799,19 @@ struct gpcg_batch_s {
 
 extern "C" {
 
-int gpcg_batch_workspace_bytes(int count, size_t *bytes) {
-  if (count < 1 || !bytes) return fail(GPCG_ERR_ARG, "count must be >= 1");
-  *bytes = tables_bytes(count);
+namespace {
+size_t batch_items(int count, const gpcg_handle *handles) {
+  size_t items = 0;
+  for (int i = 0; i < count; ++i) items += (size_t)handles[i]->L.ntiles;
+  return items;
+}
+}  // namespace
+
+int gpcg_batch_workspace_bytes(int count, const gpcg_handle *handles, size_t *bytes) {
+  if (count < 1 || !bytes || !handles) return fail(GPCG_ERR_ARG, "count >= 1 and handles required");
+  for (int i = 0; i < count; ++i)
+    if (!handles[i]) return fail(GPCG_ERR_ARG, "NULL handle in batch");
+  *bytes = tables_bytes(count, batch_items(count, handles));
   return GPCG_OK;
 }
 
@@ -771,13 +819,14 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
                       void *stream, gpcg_batch *out) {
   if (!out || count < 1 || !handles) return fail(GPCG_ERR_ARG, "bad batch arguments");
   *out = nullptr;
-  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < tables_bytes(count))
-    return fail(GPCG_ERR_WORKSPACE, "batch workspace missing, misaligned or too small");
   for (int i = 0; i < count; ++i) {
     if (!handles[i]) return fail(GPCG_ERR_ARG, "NULL handle in batch");
     if (handles[i]->st.mixed != handles[0]->st.mixed)
       return fail(GPCG_ERR_ARG, "all handles of a batch must share the precision");
   }
+  const size_t need = tables_bytes(count, batch_items(count, handles));
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < need)
+    return fail(GPCG_ERR_WORKSPACE, "batch workspace missing, misaligned or too small");
   auto *b = new gpcg_batch_s();
   b->hs.assign(handles, handles + count);
   b->stream = (hipStream_t)stream;
@@ -785,7 +834,8 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->ws_bytes = ws_bytes;
   b->qptrs = (QPDev **)b->ws;
   b->prefix = (int32_t *)(b->ws + align_up(sizeof(void *) * (size_t)count));
-  b->tbytes = tables_bytes(count);
+  b->items = (WgItem *)(b->ws + items_offset(count));
+  b->tbytes = need;
   b->mixed = handles[0]->st.mixed;
   int rc = alloc_flag(&b->flags, (size_t)count);
   if (rc) {
@@ -865,19 +915,25 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     for (int i = 0; i < cnt; ++i) active[i] = i;
     const int chunk = default_chunk(b->hs[0]->opt);
     while (!active.empty()) {
+      HIP_OK(hipStreamSynchronize(b->stream));  // the staged tables may still be in flight
       pre[0] = 0;
+      std::vector<int32_t> nt(active.size());
       for (size_t a = 0; a < active.size(); ++a) {
         qp[a] = b->hs[active[a]]->dqp;
-        pre[a + 1] = pre[a] + b->hs[active[a]]->st.ntiles;
+        nt[a] = b->hs[active[a]]->st.ntiles;
+        pre[a + 1] = pre[a] + nt[a];
       }
       const int total = pre[active.size()];
-      HIP_OK(hipStreamSynchronize(b->stream));
+      auto *items = (WgItem *)(b->stage + items_offset(cnt));
+      const int nitems = fill_items(items, qp, nt.data(), (int)active.size(), 1);
       HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
       StepLaunch SL{};
       SL.qps = b->qptrs;
-      SL.prefix = b->prefix;
+      SL.items = b->items;
       SL.nqp = (int32_t)active.size();
       SL.total_tiles = total;
+      SL.tiles_per_wg = 1;
+      SL.data_grid = nitems;
       bool spec = true;
       for (int i : active) spec = spec && spec_ok(b->hs[i]->st);
       hipGraphExec_t graph = nullptr;
@@ -980,6 +1036,8 @@ struct gpcg_server_s {
   size_t header;        // launch tables at the start of the arena
   QPDev **qptrs;
   int32_t *prefix;
+  WgItem *items;
+  size_t item_cap;
   char *stage_tables;   // pinned
   QPDev *stage;         // pinned, one per slot
   PinnedWords flags;    // one DONE word per slot
@@ -1171,7 +1229,10 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   if (opt->quantum < 0 || (opt->quantum & 1)) return fail(GPCG_ERR_ARG, "quantum must be even");
   if (!opt->arena || ((uintptr_t)opt->arena % kAlign) != 0)
     return fail(GPCG_ERR_WORKSPACE, "arena missing or not 256-byte aligned");
-  const size_t header = tables_bytes(opt->max_slots);
+  // a resident request holds at least 24 bytes per unknown (x1, g0, g1), so
+  // the arena holds at most arena / (24 * 256) tiles plus one partial tile per slot
+  const size_t item_cap = (size_t)opt->max_slots + opt->arena_bytes / (24 * (size_t)kBlock);
+  const size_t header = tables_bytes(opt->max_slots, item_cap);
   if (opt->arena_bytes <= header) return fail(GPCG_ERR_WORKSPACE, "arena too small");
   auto *s = new gpcg_server_s();
   s->opt = *opt;
@@ -1181,6 +1242,8 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   s->header = header;
   s->qptrs = (QPDev **)s->arena;
   s->prefix = (int32_t *)(s->arena + align_up(sizeof(void *) * (size_t)opt->max_slots));
+  s->items = (WgItem *)(s->arena + items_offset(opt->max_slots));
+  s->item_cap = item_cap;
   s->slots.resize(opt->max_slots);
   s->free_list[header] = opt->arena_bytes - header;
   s->tick_hz = wall_clock_hz();
@@ -1244,21 +1307,29 @@ int gpcg_server_step(gpcg_server s, int *active) {
     int cnt = 0;
     bool spec = true;
     pre[0] = 0;
+    std::vector<int32_t> nt;
     for (int i = 0; i < (int)s->slots.size(); ++i) {
       if (!s->slots[i].used) continue;
       spec = spec && req_layout(&s->slots[i].req.op, s->opt.precision).L.tile == kBlock;
       const ReqLayout R = req_layout(&s->slots[i].req.op, s->opt.precision);
       qp[cnt] = (QPDev *)(s->arena + s->slots[i].off + R.L.qp);
       pre[cnt + 1] = pre[cnt] + s->slots[i].ntiles;
+      nt.push_back(s->slots[i].ntiles);
       ++cnt;
     }
+    if ((size_t)pre[cnt] > s->item_cap)
+      return fail(GPCG_ERR_ARG, "internal: more tiles resident than the item table holds");
+    auto *items = (WgItem *)(s->stage_tables + items_offset((int)s->slots.size()));
+    const int nitems = fill_items(items, qp, nt.data(), cnt, 1);
     HIP_OK(hipMemcpyAsync(s->arena, s->stage_tables, s->header, hipMemcpyHostToDevice,
                           s->stream));
     StepLaunch SL{};
     SL.qps = s->qptrs;
-    SL.prefix = s->prefix;
+    SL.items = s->items;
     SL.nqp = cnt;
     SL.total_tiles = pre[cnt];
+    SL.tiles_per_wg = 1;
+    SL.data_grid = nitems;
     for (int k = 0; k < s->opt.quantum; ++k) {
       SL.parity = (int)(s->launches & 1);
       if (gpcg_launch_split(SL, s->opt.precision == GPCG_PREC_MIXED, spec, s->stream) != 0)

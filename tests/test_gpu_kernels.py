@@ -8,7 +8,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 2, 3, 37, 50, 129]
+SIZES = [1, 2, 3, 4, 37, 50, 64, 129]
 
 
 def _inst(N, op, seed=0):
@@ -45,12 +45,13 @@ def test_spmv_fp64(N, kind):
     s.close()
 
 
+@pytest.mark.parametrize("N", [61, 64])
 @pytest.mark.parametrize("kind", ["const", "var", "csr"])
-def test_spmv_fp32(kind):
+def test_spmv_fp32(N, kind):
     import paper_cs_0101018_amd as gpcg
     torch, dev = G.torch_dev()
     base = instances.OP_VAR if kind == "var" else instances.OP_CONST
-    inst = _inst(61, base)
+    inst = _inst(N, base)
     s = gpcg.Solver(G.operator_for(inst, kind), device=dev, precision=gpcg.GPCG_PREC_MIXED)
     v = np.random.default_rng(1).standard_normal(inst.n).astype(np.float32)
     ref = oracle.default().matvec(inst.csr(), v.astype(np.float64))
@@ -61,6 +62,37 @@ def test_spmv_fp32(kind):
     got = y.cpu().numpy().astype(np.float64)
     scale = np.abs(inst.csr()[2]).max() * np.abs(v).max()
     assert np.abs(got - ref).max() <= 1e-5 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", ["const", "var"])
+@pytest.mark.parametrize("N", [2, 4, 8, 100])
+def test_spmv_vector_kernel_bitwise(N, kind, prec):
+    """The vector-load stencil kernel (grid width a multiple of the vector
+    width, aligned arrays) and the scalar kernel (the same arrays at an odd
+    element offset) give bitwise equal products, masked and unmasked."""
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    base = instances.OP_VAR if kind == "var" else instances.OP_CONST
+    inst = _inst(N, base, seed=3)
+    s = gpcg.Solver(G.operator_for(inst, kind), device=dev, precision=prec)
+    dt = torch.float32 if prec else torch.float64
+    rng = np.random.default_rng(N)
+    n = inst.n
+    v = torch.from_numpy(rng.standard_normal(n)).to(dt).to(dev)
+    m = torch.from_numpy((rng.uniform(size=n) < 0.6).astype(np.uint8)).to(dev)
+    vb = torch.zeros(n + 1, dtype=dt, device=dev)
+    mb = torch.zeros(n + 1, dtype=torch.uint8, device=dev)
+    vb[1:] = v
+    mb[1:] = m
+    for mask, mask_odd in ((None, None), (m, mb[1:])):
+        y_vec = torch.empty(n, dtype=dt, device=dev)
+        y_odd = torch.zeros(n + 1, dtype=dt, device=dev)
+        s.spmv(v, y_vec, mask)
+        s.spmv(vb[1:], y_odd[1:], mask_odd)
+        torch.cuda.synchronize()
+        assert torch.equal(y_vec, y_odd[1:])
     s.close()
 
 

@@ -160,6 +160,7 @@ def test_fused_and_split_forms_agree_bitwise(case):
            for f in (gpcg.GPCG_FORM_FUSED, gpcg.GPCG_FORM_SPLIT)]
     res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT,
                        use_graph=0, chunk=10))
+    res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT, tiles_per_wg=3))
     (x1, g1, s1) = res[0]
     assert s1["status"] == gpcg.GPCG_OK
     for x, g, st in res[1:]:
