@@ -245,6 +245,11 @@ def bench_batch(args, gpcg, torch, dev):
             x.copy_(d[4])
         return batch.solve(probs, mode=mode)
 
+    tuned = None
+    if not args.no_autotune and mode == gpcg.GPCG_BATCH_STEPPED:
+        tuned = batch.autotune(probs, [d[4] for d in data])["chosen"]
+        log(f"autotune: {tuned}")
+
     for _ in range(args.warmup):
         run_batch()
     torch.cuda.synchronize()
@@ -270,6 +275,7 @@ def bench_batch(args, gpcg, torch, dev):
                      "achieved": round(alg_bytes / wall / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg_bytes / wall / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_batch": alg_bytes},
+        "autotune": tuned,
         "failed": len(bad),
     }
     if args.no_sequential:
@@ -381,7 +387,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="varcoef256_fp64",
                     choices=sorted(WORKLOADS) + list(BATCH_WORKLOADS) + list(SERVE_WORKLOADS))
-    ap.add_argument("--batch-mode", default="persistent", choices=["persistent", "stepped"])
+    ap.add_argument("--batch-mode", default="stepped", choices=["persistent", "stepped"])
     ap.add_argument("--requests", type=int, default=4096, help="serving: trace length")
     ap.add_argument("--form", default="auto", choices=["auto", "fused", "split"],
                     help="launch form of single-QP workloads")
@@ -390,6 +396,8 @@ def main():
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
                     help="free set of the reduced CG: byte mask or compacted list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (run during warmup, untimed)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch: skip the sequential FP64 comparison")
     ap.add_argument("--extras", action="store_true", help="also time SpMV on 1024^2/1600^2")
@@ -447,6 +455,10 @@ def main():
         x.copy_(x0)
         return solver.solve(b, l, u, x)
 
+    tuned = None
+    if not args.no_autotune and args.form == "auto" and args.tiles_per_wg == 0:
+        tuned = solver.autotune(b, l, u, x0)["chosen"]
+        log(f"autotune: {tuned}")
     for _ in range(args.warmup):
         st = step()
     torch.cuda.synchronize()
@@ -512,6 +524,7 @@ def main():
             "launches_per_solve": launches / args.steps,
             "useful_passes_per_solve": passes / args.steps,
         },
+        "autotune": tuned,
         "solve": {k: st[k] for k in ("outer_iters", "gp_iters", "cg_iters", "backtracks",
                                      "face_repeats", "passes", "launches", "pg", "tau")},
         "phase_ms": {k: round(st[k], 3) for k in ("ms_cg", "ms_gp", "ms_search", "ms_other")},

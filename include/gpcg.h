@@ -202,6 +202,39 @@ int gpcg_projected_gradient(gpcg_handle h, const double *x, const double *l, con
                             const double *g, double *pg, double *norm2, int64_t *n_lower,
                             int64_t *n_upper, int64_t *n_nonbinding);
 
+/* --------------------------------------------------------------- autotuner
+ * Picks the launch configuration of a handle by timing it: the launch form
+ * (fused, split), the consecutive tiles per data workgroup of the split form
+ * (1, 2, 4), the early loading of CG operands (stencil operators) and the
+ * number of passes per graph replay (16, 32, 64), one dimension at a time,
+ * each candidate timed on a full solve of the given problem (after one
+ * untimed solve that builds its graph).  Every configuration gives bitwise
+ * the same answer; a candidate whose answer differs is never kept and makes
+ * the call return GPCG_ERR_HIP.  The winner is kept by the handle and in a
+ * process-wide table keyed by operator shape, precision and free-set form:
+ * handles created later with GPCG_FORM_AUTO, tiles_per_wg 0 and chunk 0 start
+ * from it.  x0 is read only; x_work (device, n doubles) receives the answer.
+ * report: NULL or filled with every candidate timed and the choice. */
+#define GPCG_TUNE_MAX 32
+
+typedef struct {
+  int32_t form;         /* GPCG_FORM_FUSED or GPCG_FORM_SPLIT                 */
+  int32_t tiles_per_wg; /* split form: tiles per data workgroup              */
+  int32_t prefetch;     /* 1: CG operands loaded before the state is read    */
+  int32_t chunk;        /* passes per graph replay                           */
+  double ms;            /* wall time of one solve                            */
+} gpcg_tune_entry;
+
+typedef struct {
+  int32_t count;        /* candidates timed (entries of cand)                */
+  int32_t mismatches;   /* candidates whose answer differed (0 expected)     */
+  gpcg_tune_entry chosen;
+  gpcg_tune_entry cand[GPCG_TUNE_MAX];
+} gpcg_tune_report;
+
+int gpcg_autotune(gpcg_handle h, const double *b, const double *l, const double *u,
+                  const double *x0, double *x_work, gpcg_tune_report *report);
+
 /* -------------------------------------------------------------- batches */
 /* A batch advances many QPs (each with its own handle and workspace; all of
  * one precision) through one sequence of launches on one stream.  Results
@@ -230,6 +263,14 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace,
 /* Solves problem i with handle i for every i.  stats: NULL or `count`
  * structs.  Returns the first error status met, else GPCG_OK. */
 int gpcg_batch_solve(gpcg_batch bt, const gpcg_problem *probs, int mode, gpcg_stats *stats);
+
+/* Autotuner of the stepped batch form (see gpcg_autotune): tiles per data
+ * workgroup (1, 2, 4), early CG operand loads and passes per graph replay,
+ * each candidate timed on a full stepped solve of the batch.  x0s[i] (device,
+ * read only) is copied into probs[i].x before every candidate; probs[i].x
+ * receives the answer.  The choice is kept by the batch. */
+int gpcg_batch_autotune(gpcg_batch bt, const gpcg_problem *probs, const double *const *x0s,
+                        gpcg_tune_report *report);
 
 int gpcg_batch_destroy(gpcg_batch bt);
 

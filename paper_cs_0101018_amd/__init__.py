@@ -90,6 +90,27 @@ class gpcg_completion(C.Structure):
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+GPCG_TUNE_MAX = 32
+
+
+class gpcg_tune_entry(C.Structure):
+    _fields_ = [("form", C.c_int32), ("tiles_per_wg", C.c_int32), ("prefetch", C.c_int32),
+                ("chunk", C.c_int32), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class gpcg_tune_report(C.Structure):
+    _fields_ = [("count", C.c_int32), ("mismatches", C.c_int32), ("chosen", gpcg_tune_entry),
+                ("cand", gpcg_tune_entry * GPCG_TUNE_MAX)]
+
+    def as_dict(self):
+        return {"count": self.count, "mismatches": self.mismatches,
+                "chosen": self.chosen.as_dict(),
+                "candidates": [self.cand[i].as_dict() for i in range(self.count)]}
+
+
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 _P = C.POINTER
 _SIGS = {
@@ -106,6 +127,8 @@ _SIGS = {
     "gpcg_batch_create": (C.c_int, [C.c_int, _P(_vp), _vp, _sz, _vp, _P(_vp)]),
     "gpcg_batch_solve": (C.c_int, [_vp, _P(gpcg_problem), C.c_int, _P(gpcg_stats)]),
     "gpcg_batch_destroy": (C.c_int, [_vp]),
+    "gpcg_autotune": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _P(gpcg_tune_report)]),
+    "gpcg_batch_autotune": (C.c_int, [_vp, _P(gpcg_problem), _P(_vp), _P(gpcg_tune_report)]),
     "gpcg_server_footprint": (C.c_int, [_P(gpcg_operator), C.c_int, _P(_sz)]),
     "gpcg_server_create": (C.c_int, [_P(gpcg_server_options), _vp, _P(_vp)]),
     "gpcg_server_submit": (C.c_int, [_vp, _P(gpcg_request)]),
@@ -230,6 +253,15 @@ class Solver:
         check(rc, "gpcg_solve")
         return st.as_dict()
 
+    def autotune(self, b, l, u, x0, x_work=None) -> dict:
+        """Times the launch configurations on this problem and keeps the
+        fastest (gpcg_autotune); returns the report.  x0 is not modified."""
+        x = x_work if x_work is not None else _torch().empty_like(x0)
+        rep = gpcg_tune_report()
+        check(_lib.gpcg_autotune(self.handle, _dptr(b), _dptr(l), _dptr(u), _dptr(x0),
+                                 _dptr(x), C.byref(rep)), "gpcg_autotune")
+        return rep.as_dict()
+
     def spmv(self, v, y, mask=None):
         fn = _lib.gpcg_spmv_f32 if v.dtype.itemsize == 4 else _lib.gpcg_spmv
         check(fn(self.handle, _dptr(v), _dptr(y), _dptr(mask)), "gpcg_spmv")
@@ -281,6 +313,20 @@ class Batch:
         stats = (gpcg_stats * cnt)()
         check(_lib.gpcg_batch_solve(self.handle, probs, mode, stats), "gpcg_batch_solve")
         return [s.as_dict() for s in stats]
+
+    def autotune(self, problems, x0s) -> dict:
+        """Times the stepped-form launch configurations (gpcg_batch_autotune)
+        and keeps the fastest; x0s are copied into the problems' x first."""
+        cnt = len(self.solvers)
+        probs = (gpcg_problem * cnt)()
+        for i, p in enumerate(problems):
+            b, l, u, x = p[:4]
+            probs[i] = gpcg_problem(_dptr(b), _dptr(l), _dptr(u), _dptr(x), None)
+        arr = (C.c_void_p * cnt)(*[_dptr(x) for x in x0s])
+        rep = gpcg_tune_report()
+        check(_lib.gpcg_batch_autotune(self.handle, probs, arr, C.byref(rep)),
+              "gpcg_batch_autotune")
+        return rep.as_dict()
 
     def close(self):
         if self.handle:

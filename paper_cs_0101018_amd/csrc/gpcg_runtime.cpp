@@ -15,8 +15,10 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "gpcg.h"
@@ -390,6 +392,37 @@ bool spec_ok(const QPStatic &s) {
 
 // ------------------------------------------------------------------ handle
 
+// How a QP's passes are launched.  Every configuration gives bitwise the
+// same answer (same tiles, same summation orders); only the speed differs.
+struct LaunchCfg {
+  int split;         // 0: fused form, 1: split form
+  int tiles_per_wg;  // split form: consecutive tiles per data workgroup
+  int spec;          // CG operands loaded before the state is known (stencils)
+  int chunk;         // passes per graph replay / host check (even)
+  bool operator==(const LaunchCfg &o) const {
+    return split == o.split && tiles_per_wg == o.tiles_per_wg && spec == o.spec &&
+           chunk == o.chunk;
+  }
+  bool operator!=(const LaunchCfg &o) const { return !(*this == o); }
+};
+
+namespace {
+
+// Tuned configurations by operator shape and precision, shared by the handles
+// of the process (handles created with automatic options start from them).
+struct TuneKey {
+  int kind, nx, ny, mixed, list;
+  int64_t n, nnz;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(kind, nx, ny, mixed, list, n, nnz) <
+           std::tie(o.kind, o.nx, o.ny, o.mixed, o.list, o.n, o.nnz);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, LaunchCfg> g_tuned;
+
+}  // namespace
+
 struct gpcg_handle_s {
   gpcg_operator op;
   gpcg_options opt;
@@ -402,14 +435,18 @@ struct gpcg_handle_s {
   QPDev *stage;         // pinned host staging for uploads / downloads
   PinnedWords flag;     // DONE flag written by the device
   hipGraphExec_t graph = nullptr;
-  int graph_chunk = 0;
+  LaunchCfg graph_cfg{};  // configuration the graph was built for
   hipEvent_t ev[2] = {nullptr, nullptr};
   double tick_hz;
-  int split;            // launch form of this handle's solves
-  int tiles_per_wg;     // split form: consecutive tiles per data workgroup
+  LaunchCfg cfg{};        // launch configuration of this handle's solves
 };
 
 namespace {
+
+TuneKey tune_key(const gpcg_handle_s *h) {
+  return TuneKey{h->op.kind, h->st.nx, h->st.ny, h->st.mixed, h->st.list ? 1 : 0, h->st.n,
+                 h->op.kind == GPCG_OP_CSR ? h->op.nnz : 0};
+}
 
 void fill_static(gpcg_handle_s *h) {
   QPStatic &q = h->st;
@@ -564,9 +601,16 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
     return cleanup(fail(GPCG_ERR_HIP, "hipHostMalloc of the staging state failed"));
   h->stage = (QPDev *)st;
   fill_static(h);
-  h->split = o.form == GPCG_FORM_SPLIT ||
-             (o.form == GPCG_FORM_AUTO && h->L.ntiles > kFusedMaxTiles);
-  h->tiles_per_wg = o.tiles_per_wg > 0 ? o.tiles_per_wg : 1;
+  h->cfg.split = o.form == GPCG_FORM_SPLIT ||
+                 (o.form == GPCG_FORM_AUTO && h->L.ntiles > kFusedMaxTiles);
+  h->cfg.tiles_per_wg = o.tiles_per_wg > 0 ? o.tiles_per_wg : 1;
+  h->cfg.spec = spec_ok(h->st) ? 1 : 0;
+  h->cfg.chunk = default_chunk(o);
+  if (o.form == GPCG_FORM_AUTO && o.tiles_per_wg == 0 && o.chunk == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(h));
+    if (it != g_tuned.end()) h->cfg = it->second;
+  }
   if (hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "hipEventCreate failed"));
@@ -616,19 +660,20 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   SL.single = h->dqp;
   SL.nqp = 1;
   SL.total_tiles = h->L.ntiles;
-  SL.tiles_per_wg = h->tiles_per_wg;
-  SL.data_grid = (h->L.ntiles + h->tiles_per_wg - 1) / h->tiles_per_wg;
-  const int chunk = default_chunk(h->opt);
-  if (h->opt.use_graph && (!h->graph || h->graph_chunk != chunk)) {
+  const LaunchCfg c = h->cfg;
+  SL.tiles_per_wg = c.tiles_per_wg;
+  SL.data_grid = (h->L.ntiles + c.tiles_per_wg - 1) / c.tiles_per_wg;
+  const int chunk = c.chunk;
+  if (h->opt.use_graph && (!h->graph || h->graph_cfg != c)) {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
-    rc = build_chain_graph(SL, h->st.mixed, spec_ok(h->st), h->split, chunk, &h->graph);
+    rc = build_chain_graph(SL, h->st.mixed, c.spec, c.split, chunk, &h->graph);
     if (rc) return rc;
-    h->graph_chunk = chunk;
+    h->graph_cfg = c;
   }
   int64_t launches = 0, checks = 0;
   volatile int32_t *flag = h->flag.host;
-  rc = run_until(h->stream, SL, h->st.mixed, spec_ok(h->st), h->split, chunk,
+  rc = run_until(h->stream, SL, h->st.mixed, c.spec, c.split, chunk,
                  h->opt.use_graph ? h->graph : nullptr, h->ev,
                  [&] { return *flag != 0; }, (int64_t)1 << 26, &launches, &checks);
   if (rc) return rc;
@@ -644,6 +689,118 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   }
   if (d.status < 0) g_last_error = gpcg_status_string(d.status);
   return d.status;
+}
+
+namespace {
+
+// Times one solve of the problem under configuration c (the first solve under
+// a configuration builds its graph and is not timed).
+int timed_solve(gpcg_handle h, const LaunchCfg &c, const double *b, const double *l,
+                const double *u, const double *x0, double *x, double *ms) {
+  const LaunchCfg keep = h->cfg;
+  h->cfg = c;
+  double best = 1e300;
+  int rc = GPCG_OK;
+  for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
+    if (hipMemcpyAsync(x, x0, sizeof(double) * (size_t)h->st.n, hipMemcpyDeviceToDevice,
+                       h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      rc = fail(GPCG_ERR_HIP, "copy of x0 failed in autotune");
+      break;
+    }
+    const double t0 = now_s();
+    rc = gpcg_solve(h, b, l, u, x, nullptr, nullptr);
+    const double t = (now_s() - t0) * 1e3;
+    if (rep == 1) best = t;
+  }
+  h->cfg = keep;
+  *ms = best;
+  return rc;
+}
+
+void note(gpcg_tune_report *r, const LaunchCfg &c, double ms) {
+  if (!r || r->count >= GPCG_TUNE_MAX) return;
+  gpcg_tune_entry &e = r->cand[r->count++];
+  e.form = c.split ? GPCG_FORM_SPLIT : GPCG_FORM_FUSED;
+  e.tiles_per_wg = c.tiles_per_wg;
+  e.prefetch = c.spec;
+  e.chunk = c.chunk;
+  e.ms = ms;
+}
+
+}  // namespace
+
+int gpcg_autotune(gpcg_handle h, const double *b, const double *l, const double *u,
+                  const double *x0, double *x_work, gpcg_tune_report *report) {
+  if (!h || !b || !l || !u || !x0 || !x_work)
+    return fail(GPCG_ERR_ARG, "handle, b, l, u, x0 and x_work are required");
+  if (report) std::memset(report, 0, sizeof(*report));
+  const size_t n = (size_t)h->st.n;
+  std::vector<double> first(n), other(n);
+  LaunchCfg best = h->cfg;
+  double best_ms = 0.0;
+  int rc = timed_solve(h, best, b, l, u, x0, x_work, &best_ms);
+  if (rc < 0) return rc;
+  note(report, best, best_ms);
+  HIP_OK(hipMemcpy(first.data(), x_work, sizeof(double) * n, hipMemcpyDeviceToHost));
+  int mismatches = 0;
+  auto consider = [&](LaunchCfg c) -> int {
+    if (c == best) return GPCG_OK;
+    double ms = 0.0;
+    const int r = timed_solve(h, c, b, l, u, x0, x_work, &ms);
+    if (r < 0) return r;
+    note(report, c, ms);
+    HIP_OK(hipMemcpy(other.data(), x_work, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (std::memcmp(first.data(), other.data(), sizeof(double) * n) != 0) {
+      ++mismatches;  // configurations must agree bitwise: never keep one that does not
+      return GPCG_OK;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+    return GPCG_OK;
+  };
+  // one dimension at a time: launch form, tiles per data workgroup, operand
+  // prefetch, chunk length
+  if (h->L.ntiles <= 4 * kFusedMaxTiles) {
+    LaunchCfg c = best;
+    c.split = best.split ? 0 : 1;
+    c.tiles_per_wg = 1;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  if (best.split)
+    for (int t : {1, 2, 4})
+      if (t <= h->L.ntiles) {
+        LaunchCfg c = best;
+        c.tiles_per_wg = t;
+        if ((rc = consider(c)) < 0) return rc;
+      }
+  if (spec_ok(h->st)) {
+    LaunchCfg c = best;
+    c.spec = best.spec ? 0 : 1;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  for (int ch : {16, 32, 64}) {
+    LaunchCfg c = best;
+    c.chunk = ch;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  h->cfg = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key(h)] = best;
+  }
+  if (report) {
+    report->mismatches = mismatches;
+    report->chosen.form = best.split ? GPCG_FORM_SPLIT : GPCG_FORM_FUSED;
+    report->chosen.tiles_per_wg = best.tiles_per_wg;
+    report->chosen.prefetch = best.spec;
+    report->chosen.chunk = best.chunk;
+    report->chosen.ms = best_ms;
+  }
+  if (mismatches) return fail(GPCG_ERR_HIP, "autotune: launch configurations disagreed");
+  return GPCG_OK;
 }
 
 // Grid width for the vector-load SpMV kernel, or 0 to use the scalar one
@@ -795,6 +952,7 @@ struct gpcg_batch_s {
   PinnedWords flags;   // one DONE word per QP
   hipEvent_t ev[2] = {nullptr, nullptr};
   int mixed;
+  LaunchCfg cfg{};     // stepped form: always split; tiles, prefetch, chunk tunable
 };
 
 extern "C" {
@@ -837,6 +995,7 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->items = (WgItem *)(b->ws + items_offset(count));
   b->tbytes = need;
   b->mixed = handles[0]->st.mixed;
+  b->cfg = LaunchCfg{1, 1, 1, default_chunk(handles[0]->opt)};
   int rc = alloc_flag(&b->flags, (size_t)count);
   if (rc) {
     delete b;
@@ -913,7 +1072,8 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     // complete (results do not depend on the launch composition)
     std::vector<int> active(cnt);
     for (int i = 0; i < cnt; ++i) active[i] = i;
-    const int chunk = default_chunk(b->hs[0]->opt);
+    const int chunk = b->cfg.chunk;
+    const int T = b->cfg.tiles_per_wg;
     while (!active.empty()) {
       HIP_OK(hipStreamSynchronize(b->stream));  // the staged tables may still be in flight
       pre[0] = 0;
@@ -925,16 +1085,16 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       }
       const int total = pre[active.size()];
       auto *items = (WgItem *)(b->stage + items_offset(cnt));
-      const int nitems = fill_items(items, qp, nt.data(), (int)active.size(), 1);
+      const int nitems = fill_items(items, qp, nt.data(), (int)active.size(), T);
       HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
       StepLaunch SL{};
       SL.qps = b->qptrs;
       SL.items = b->items;
       SL.nqp = (int32_t)active.size();
       SL.total_tiles = total;
-      SL.tiles_per_wg = 1;
+      SL.tiles_per_wg = T;
       SL.data_grid = nitems;
-      bool spec = true;
+      bool spec = b->cfg.spec != 0;
       for (int i : active) spec = spec && spec_ok(b->hs[i]->st);
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
@@ -974,6 +1134,87 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
   }
   if (first_err < 0) g_last_error = gpcg_status_string(first_err);
   return first_err;
+}
+
+int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *const *x0s,
+                        gpcg_tune_report *report) {
+  if (!b || !probs || !x0s) return fail(GPCG_ERR_ARG, "batch, problems and x0s are required");
+  if (report) std::memset(report, 0, sizeof(*report));
+  const int cnt = (int)b->hs.size();
+  size_t total = 0;
+  for (int i = 0; i < cnt; ++i) {
+    if (!x0s[i] || !probs[i].x) return fail(GPCG_ERR_ARG, "x0s[i] and probs[i].x are required");
+    total += (size_t)b->hs[i]->st.n;
+  }
+  std::vector<double> first(total), other(total);
+  auto run = [&](const LaunchCfg &c, double *ms, std::vector<double> &out) -> int {
+    const LaunchCfg keep = b->cfg;
+    b->cfg = c;
+    for (int i = 0; i < cnt; ++i)
+      HIP_OK(hipMemcpyAsync(probs[i].x, x0s[i], sizeof(double) * (size_t)b->hs[i]->st.n,
+                            hipMemcpyDeviceToDevice, b->stream));
+    HIP_OK(hipStreamSynchronize(b->stream));
+    const double t0 = now_s();
+    const int rc = gpcg_batch_solve(b, probs, GPCG_BATCH_STEPPED, nullptr);
+    *ms = (now_s() - t0) * 1e3;
+    b->cfg = keep;
+    if (rc < 0) return rc;
+    size_t off = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const size_t n = (size_t)b->hs[i]->st.n;
+      HIP_OK(hipMemcpy(out.data() + off, probs[i].x, sizeof(double) * n, hipMemcpyDeviceToHost));
+      off += n;
+    }
+    return GPCG_OK;
+  };
+  LaunchCfg best = b->cfg;
+  double best_ms = 0.0;
+  int rc = run(best, &best_ms, first);
+  if (rc < 0) return rc;
+  note(report, best, best_ms);
+  int mismatches = 0;
+  auto consider = [&](LaunchCfg c) -> int {
+    if (c == best) return GPCG_OK;
+    double ms = 0.0;
+    const int r = run(c, &ms, other);
+    if (r < 0) return r;
+    note(report, c, ms);
+    if (std::memcmp(first.data(), other.data(), sizeof(double) * total) != 0) {
+      ++mismatches;
+      return GPCG_OK;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+    return GPCG_OK;
+  };
+  for (int t : {1, 2, 4}) {
+    LaunchCfg c = best;
+    c.tiles_per_wg = t;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  {
+    LaunchCfg c = best;
+    c.spec = best.spec ? 0 : 1;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  for (int ch : {16, 32, 64}) {
+    LaunchCfg c = best;
+    c.chunk = ch;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  b->cfg = best;
+  if (report) {
+    report->mismatches = mismatches;
+    report->chosen.form = GPCG_FORM_SPLIT;
+    report->chosen.tiles_per_wg = best.tiles_per_wg;
+    report->chosen.prefetch = best.spec;
+    report->chosen.chunk = best.chunk;
+    report->chosen.ms = best_ms;
+  }
+  if (mismatches) return fail(GPCG_ERR_HIP, "batch autotune: launch configurations disagreed");
+  return GPCG_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,67 @@
+"""The autotuner (gpcg_autotune, gpcg_batch_autotune): every launch
+configuration it times gives bitwise the same answer, and the configuration
+it keeps solves the problem exactly as before tuning."""
+import numpy as np
+import pytest
+
+import instances
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("case", ["ragged_fp64", "ragged_mixed", "csr_fp64", "c1_fp64"])
+def test_autotune_keeps_the_answer(case):
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    inst, kind, prec = {
+        "ragged_fp64": (instances.obstacle(77, 3, amplitude=0.45), None, 0),
+        "ragged_mixed": (instances.obstacle(77, 3, amplitude=0.45), None, 1),
+        "csr_fp64": (instances.obstacle(61, 2), "csr", 0),
+        "c1_fp64": (instances.varcoef256(0), None, 0),
+    }[case]
+    x_ref, _, st_ref = G.solve(inst, kind, precision=prec)
+    s = gpcg.Solver(G.operator_for(inst, kind), device=dev, precision=prec)
+    b, l, u, x0 = (G.to_dev(a) for a in (inst.b, inst.l, inst.u, inst.x0))
+    rep = s.autotune(b, l, u, x0)
+    print(f"{case}: {rep['count']} candidates, chosen {rep['chosen']}", flush=True)
+    assert rep["mismatches"] == 0
+    assert rep["count"] >= 3
+    assert np.array_equal(x0.cpu().numpy(), inst.x0)  # x0 is read only
+    x = x0.clone()
+    st = s.solve(b, l, u, x)
+    torch.cuda.synchronize()
+    assert st["status"] == gpcg.GPCG_OK
+    assert np.array_equal(x.cpu().numpy(), x_ref)
+    assert st["cg_iters"] == st_ref["cg_iters"]
+    s.close()
+    # a handle created afterwards with automatic options starts from the
+    # tuned configuration and still gives the same answer
+    x2, _, _ = G.solve(inst, kind, precision=prec)
+    assert np.array_equal(x2, x_ref)
+
+
+def test_batch_autotune_keeps_the_answer():
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    insts = [instances.obstacle(N, 11 + N, amplitude=0.35) for N in (40, 75, 33)]
+    insts.append(instances.varcoef(48, 5))
+    alone = [G.solve(i)[0] for i in insts]
+    solvers = [gpcg.Solver(G.operator_for(i), device=dev) for i in insts]
+    x0s = [G.to_dev(i.x0) for i in insts]
+    xs = [x.clone() for x in x0s]
+    probs = [(G.to_dev(i.b), G.to_dev(i.l), G.to_dev(i.u), x) for i, x in zip(insts, xs)]
+    bt = gpcg.Batch(solvers, device=dev)
+    rep = bt.autotune(probs, x0s)
+    print(f"batch: {rep['count']} candidates, chosen {rep['chosen']}", flush=True)
+    assert rep["mismatches"] == 0 and rep["count"] >= 3
+    for x, x0 in zip(xs, x0s):
+        x.copy_(x0)
+    stats = bt.solve(probs, mode=gpcg.GPCG_BATCH_STEPPED)
+    torch.cuda.synchronize()
+    for x, a, st in zip(xs, alone, stats):
+        assert st["status"] == gpcg.GPCG_OK
+        assert np.array_equal(x.cpu().numpy(), a)
+    bt.close()
+    for s in solvers:
+        s.close()
