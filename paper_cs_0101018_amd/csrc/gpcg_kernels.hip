@@ -803,12 +803,19 @@ __device__ __forceinline__ void copy_dyn(const QPDyn *src, QPDyn *dst) {
 // latency behind the slot reduction and the transition.
 template <typename CT>
 struct CGOperands {
-  CT r, u, s, p, w;      // rho, A rho, A p (previous), p, w at k
-  CT rn[4], un[4], sn[4];  // rho, A rho, A p at the W, E, S, N neighbours (0 outside)
-  CT wt[4];              // edge weights W, E, S, N (variable stencil)
-  int m;                 // free-set mask at k
+  CT r, u, s, p, w;    // rho, A rho, A p (previous), p, w at k
+  CT rS, uS, sS;       // the same three at the south neighbour k - nx (0 outside)
+  CT rN, uN, sN;       // and at the north neighbour k + nx
+  CT rX, uX, sX;       // first / last thread of the tile: at k - 1 / k + 1 (0 otherwise)
+  CT wt[4];            // edge weights W, E, S, N (variable stencil)
+  int m;               // free-set mask at k
+  bool hasW, hasE, hasS, hasN;
 };
 
+// Loads the operands of one CG iteration at unknown k of a tile of kBlock
+// consecutive unknowns.  The west and east neighbours are the neighbouring
+// threads of the tile (exchanged through LDS after the update); only the
+// first and last threads load the row outside the tile.
 template <typename CT>
 __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t k,
                                             CGOperands<CT> &P) {
@@ -825,46 +832,62 @@ __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t
   const int32_t nx = A.nx;
   const int32_t j = (int32_t)(((uint64_t)k * A.magic) >> A.shift);
   const int32_t i = (int32_t)(k - (int64_t)j * nx);
-  const int64_t nb[4] = {k - 1, k + 1, k - nx, k + nx};
-  const bool has[4] = {i > 0, i < nx - 1, j > 0, j < A.ny - 1};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    P.rn[q] = has[q] ? ro[nb[q]] : CT(0);
-    P.un[q] = has[q] ? uo[nb[q]] : CT(0);
-    P.sn[q] = has[q] ? so[nb[q]] : CT(0);
-  }
+  P.hasW = i > 0;
+  P.hasE = i < nx - 1;
+  P.hasS = j > 0;
+  P.hasN = j < A.ny - 1;
+  P.rS = P.hasS ? ro[k - nx] : CT(0);
+  P.uS = P.hasS ? uo[k - nx] : CT(0);
+  P.sS = P.hasS ? so[k - nx] : CT(0);
+  P.rN = P.hasN ? ro[k + nx] : CT(0);
+  P.uN = P.hasN ? uo[k + nx] : CT(0);
+  P.sN = P.hasN ? so[k + nx] : CT(0);
+  int64_t kx = -1;
+  if (threadIdx.x == 0 && P.hasW) kx = k - 1;
+  if (threadIdx.x == kBlock - 1 && P.hasE) kx = k + 1;
+  P.rX = kx >= 0 ? ro[kx] : CT(0);
+  P.uX = kx >= 0 ? uo[kx] : CT(0);
+  P.sX = kx >= 0 ? so[kx] : CT(0);
   if (A.kind == OPK_VAR) {
     const int64_t ex = (int64_t)j * (nx + 1) + i;
-    const int64_t ey = (int64_t)j * nx + i;
     P.wt[0] = A.wx[ex];
     P.wt[1] = A.wx[ex + 1];
-    P.wt[2] = A.wy[ey];
-    P.wt[3] = A.wy[ey + nx];
+    P.wt[2] = A.wy[k];
+    P.wt[3] = A.wy[k + nx];
   }
 }
 
-// The CG iteration of run_pass for one unknown, on prefetched operands.  Same
-// formulas in the same order as the generic path (bitwise equal results).
+// The CG iteration of run_pass on the prefetched operands of a tile, for
+// every thread of the workgroup (own: k is an unknown of the QP).  Every
+// updated residual rho_{i+1} is computed once, by its owner, and read by its
+// west and east neighbours from LDS; the formulas and their order are those
+// of the generic path, so the results are bitwise equal to it.
 template <typename CT>
 __device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCore &d, int lpar,
-                                                   int64_t k, const CGOperands<CT> &P, CT &gam,
-                                                   CT &del) {
-  if (!P.m) return;
+                                                   int64_t k, bool own, const CGOperands<CT> &P,
+                                                   CT &gam, CT &del) {
+  __shared__ CT s_r1[kBlock];
   const bool first = d.first != 0;
   const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
+  // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i
+  auto rnew = [&](CT r, CT u, CT sv) { return fmaT<CT>(-al, first ? u : fmaT<CT>(be, sv, u), r); };
   const CT sk = first ? P.u : fmaT<CT>(be, P.s, P.u);
   const CT r1 = fmaT<CT>(-al, sk, P.r);
+  s_r1[threadIdx.x] = own ? r1 : CT(0);
+  __syncthreads();
+  const int t = (int)threadIdx.x;
+  CT v[4];
+  v[0] = !P.hasW ? CT(0) : (t > 0 ? s_r1[t - 1] : rnew(P.rX, P.uX, P.sX));
+  v[1] = !P.hasE ? CT(0) : (t < kBlock - 1 ? s_r1[t + 1] : rnew(P.rX, P.uX, P.sX));
+  v[2] = P.hasS ? rnew(P.rS, P.uS, P.sS) : CT(0);
+  v[3] = P.hasN ? rnew(P.rN, P.uN, P.sN) : CT(0);
+  __syncthreads();  // s_r1 is rewritten by the next tile
+  if (!own || !P.m) return;
   const CT pk = first ? P.r : fmaT<CT>(be, P.p, P.r);
   ((CT *)S->wv)[k] = fmaT<CT>(al, pk, P.w);
   ((CT *)S->pv)[k] = pk;
   ((CT *)S->sq[lpar ^ 1])[k] = sk;
   ((CT *)S->rho[lpar ^ 1])[k] = r1;
-  CT v[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const CT sq = first ? P.un[q] : fmaT<CT>(be, P.sn[q], P.un[q]);
-    v[q] = fmaT<CT>(-al, sq, P.rn[q]);
-  }
   CT u1;
   if (S->op_kind == OPK_CONST) {
     const OpView<CT> A = op_view<CT>(S);
@@ -898,7 +921,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   // SPEC launches hold only stencil QPs with one unknown per thread
   const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
   const bool own = SPEC && kk < S->n;
-  CGOperands<CT> P;
+  CGOperands<CT> P{};
   if (own) cg_prefetch<CT>(S, par, kk, P);
   copy_dyn(&q->dyn[par], &sd);
   __syncthreads();
@@ -925,7 +948,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
     if (SPEC && phase == PH_CG_ITER) {
       CT gam = CT(0), del = CT(0);
-      if (own) cg_iter_prefetched<CT>(S, sd.c, par, kk, P, gam, del);
+      cg_iter_prefetched<CT>(S, sd.c, par, kk, own, P, gam, del);
       if (sizeof(CT) == 4) {
         accf[0] = (float)gam;
         accf[1] = (float)del;
@@ -992,7 +1015,11 @@ constexpr int kCoreWords = (int)(sizeof(QPCore) / 4);
 static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 
 // One workgroup per work item: a run of consecutive tiles of one QP (one QP:
-// tiles_per_wg tiles per workgroup; several QPs: the item table).
+// tiles_per_wg tiles per workgroup; several QPs: the item table).  CG
+// iterations of stencil QPs in the mask form take the lean path (operands of
+// the tile, neighbours exchanged through LDS); with SPEC its loads for the
+// first tile are issued before the state is read, which costs registers in
+// every phase.
 template <typename CT, bool SPEC>
 __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
@@ -1012,9 +1039,9 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   const QPStatic *S = &q->st;
   const int par = L.parity;
   int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
-  bool own = SPEC && kk < S->n;
-  CGOperands<CT> P;
-  if (own) cg_prefetch<CT>(S, par, kk, P);
+  bool own = kk < S->n;
+  CGOperands<CT> P{};
+  if (SPEC && own) cg_prefetch<CT>(S, par, kk, P);
   if (threadIdx.x < kCoreWords)
     reinterpret_cast<uint32_t *>(&sc)[threadIdx.x] =
         reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c)[threadIdx.x];
@@ -1024,6 +1051,29 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   const int mixed = S->mixed, ntiles = S->ntiles;
   double *slots = tile_slots(q);
   const int t1 = t0 + nt < ntiles ? t0 + nt : ntiles;
+  const bool lean = SPEC || (S->op_kind != OPK_CSR && S->list == nullptr && S->tile == kBlock);
+  if (phase == PH_CG_ITER && lean) {
+    for (int tile = t0; tile < t1; ++tile) {
+      if (!SPEC || tile != t0) {
+        kk = (int64_t)tile * kBlock + threadIdx.x;
+        own = kk < S->n;
+        if (own) cg_prefetch<CT>(S, par, kk, P);
+      }
+      CT gam = CT(0), del = CT(0);
+      cg_iter_prefetched<CT>(S, sc, par, kk, own, P, gam, del);
+      double acc[kNP];
+      float accf[2] = {(float)gam, (float)del};
+#pragma unroll
+      for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
+      if (sizeof(CT) == 8) {
+        acc[0] = (double)gam;
+        acc[1] = (double)del;
+      }
+      write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
+      if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
+    }
+    return;
+  }
   for (int tile = t0; tile < t1; ++tile) {
     const int64_t k0 = (int64_t)tile * S->tile;
     const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
@@ -1031,24 +1081,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     float accf[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-    if (SPEC && phase == PH_CG_ITER) {
-      if (tile != t0) {
-        kk = k0 + threadIdx.x;
-        own = kk < S->n;
-        if (own) cg_prefetch<CT>(S, par, kk, P);
-      }
-      CT gam = CT(0), del = CT(0);
-      if (own) cg_iter_prefetched<CT>(S, sc, par, kk, P, gam, del);
-      if (sizeof(CT) == 4) {
-        accf[0] = (float)gam;
-        accf[1] = (float)del;
-      } else {
-        acc[0] = (double)gam;
-        acc[1] = (double)del;
-      }
-    } else {
-      run_pass<CT>(S, slots, sc, phase, par, k0, k1, acc, accf);
-    }
+    run_pass<CT>(S, slots, sc, phase, par, k0, k1, acc, accf);
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
   }
