@@ -93,9 +93,10 @@ struct QPDev {
   uint32_t pad[63];
 };
 
-// The tile slots of a QP follow its QPDev at a fixed offset, laid out
-// [max(ntiles, kBlock)][2 parities][kNP] doubles, so a workgroup can fetch
-// the state and its slot in one round trip (slot tid always exists).
+// The tile slots of a QP follow its QPDev at a fixed offset.  They are laid
+// out in blocks of kBlock tiles, [tile / kBlock][2 parities][kNP][tile %
+// kBlock] doubles, so the threads of a workgroup that read the slots of
+// consecutive tiles read consecutive words, and at least one block exists.
 constexpr size_t kQPDevBytes = (sizeof(QPDev) + 255) / 256 * 256;
 
 __host__ __device__ inline double *tile_slots(QPDev *q) {
@@ -104,12 +105,14 @@ __host__ __device__ inline double *tile_slots(QPDev *q) {
 __host__ __device__ inline const double *tile_slots(const QPDev *q) {
   return reinterpret_cast<const double *>(reinterpret_cast<const char *>(q) + kQPDevBytes);
 }
+__host__ __device__ inline int64_t slot_index(int tile, int par, int k) {
+  return (((int64_t)(tile / kBlock) * 2 + par) * kNP + k) * kBlock + (tile % kBlock);
+}
 __host__ __device__ inline size_t tile_slot_bytes(int ntiles) {
-  return sizeof(double) * 2 * kNP * (size_t)(ntiles > kBlock ? ntiles : kBlock);
+  const size_t blocks = ntiles > kBlock ? ((size_t)ntiles + kBlock - 1) / kBlock : 1;
+  return sizeof(double) * 2 * kNP * kBlock * blocks;
 }
 
-// Work of one data-kernel workgroup in a launch over several QPs: the tiles
-// tile0 .. tile0 + ntile - 1 of QP q.
 struct WgItem {
   QPDev *q;
   int32_t tile0, ntile;

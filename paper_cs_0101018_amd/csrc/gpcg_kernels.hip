@@ -289,16 +289,14 @@ __device__ __forceinline__ void write_partial(double *slots, int par, int phase,
   const int ns = nslots(phase);
   block_slots(ns, f32, acc, accf);
   if (threadIdx.x == 0) {
-    double *slot = slots + ((int64_t)tile * 2 + par) * kNP;
-    for (int k = 0; k < ns; ++k) slot[k] = acc[k];
+    for (int k = 0; k < ns; ++k) slots[slot_index(tile, par, k)] = acc[k];
   }
 }
 
 // Loads slot `tid` of parity par (always present) ahead of time.
 __device__ __forceinline__ void prefetch_slot(const double *slots, int par, double (&pf)[kNP]) {
-  const double *slot = slots + ((int64_t)threadIdx.x * 2 + par) * kNP;
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) pf[k] = slot[k];
+  for (int k = 0; k < kNP; ++k) pf[k] = slots[slot_index((int)threadIdx.x, par, k)];
 }
 
 // Adds slots t = tid + 256, tid + 512, ... (in that order) of parity par to
@@ -312,7 +310,7 @@ __device__ __forceinline__ void sum_slot_tail(const double *slots, int par, int 
 #pragma unroll
     for (int u = 0; u < D; ++u)
 #pragma unroll
-      for (int k = 0; k < NS; ++k) buf[u][k] = slots[((int64_t)(t + u * kBlock) * 2 + par) * kNP + k];
+      for (int k = 0; k < NS; ++k) buf[u][k] = slots[slot_index(t + u * kBlock, par, k)];
 #pragma unroll
     for (int u = 0; u < D; ++u) {
 #pragma unroll
@@ -322,17 +320,21 @@ __device__ __forceinline__ void sum_slot_tail(const double *slots, int par, int 
     }
   }
   for (; t < ntiles; t += kBlock) {
-    const double *slot = slots + ((int64_t)t * 2 + par) * kNP;
+    double v[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) res[k] += slot[k];
-    vf[0] += (float)slot[0];
-    vf[1] += (float)slot[1];
+    for (int k = 0; k < NS; ++k) v[k] = slots[slot_index(t, par, k)];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) res[k] += v[k];
+    vf[0] += (float)v[0];
+    vf[1] += (float)v[1];
   }
 }
 
 // Sums the ntiles slots of parity par that pass `phase` filled, in tile
 // order (thread tid takes tiles tid, tid + 256, ...; slot tid prefetched in
-// pf); the result is valid in thread 0's res.
+// pf); the result is valid in thread 0's res.  DEEP keeps more loads in
+// flight (the transition kernel, where registers are plentiful).
+template <bool DEEP = false>
 __device__ __forceinline__ void sum_partials(const double *slots, int par, int ntiles, int phase,
                                              bool f32, const double (&pf)[kNP],
                                              double (&res)[kNP]) {
@@ -344,9 +346,9 @@ __device__ __forceinline__ void sum_partials(const double *slots, int par, int n
   vf[0] = mine ? (float)pf[0] : 0.0f;
   vf[1] = mine ? (float)pf[1] : 0.0f;
   if (ntiles > kBlock) {
-    if (ns == 2) sum_slot_tail<2>(slots, par, ntiles, res, vf);
-    else if (ns == 3) sum_slot_tail<3>(slots, par, ntiles, res, vf);
-    else sum_slot_tail<kNP>(slots, par, ntiles, res, vf);
+    if (ns == 2) sum_slot_tail<2, DEEP ? 16 : 8>(slots, par, ntiles, res, vf);
+    else if (ns == 3) sum_slot_tail<3, DEEP ? 12 : 8>(slots, par, ntiles, res, vf);
+    else sum_slot_tail<kNP, DEEP ? 4 : 2>(slots, par, ntiles, res, vf);
   }
   block_slots(ns, f32, res, vf);
 }
@@ -488,7 +490,7 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       const int tile = (int)(k0 / kBlock);
       double before[1] = {0.0};
       for (int t = (int)threadIdx.x; t < tile; t += kBlock)
-        before[0] += slots[((int64_t)t * 2 + lpar) * kNP + 2];
+        before[0] += slots[slot_index(t, lpar, 2)];
       block_sum<double, 1>(before);
       __shared__ int64_t s_base;
       __shared__ int s_wave[kBlock / 64];
@@ -993,7 +995,7 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   __syncthreads();
   if (sd.c.pending) {
     double R[kNP];
-    sum_partials(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
+    sum_partials<true>(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
     if (threadIdx.x == 0) {
       advance(S, sd, R, clk);
       sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
