@@ -300,33 +300,27 @@ __device__ __forceinline__ void prefetch_slot(const double *slots, int par, doub
 }
 
 // Adds slots t = tid + 256, tid + 512, ... (in that order) of parity par to
-// res / vf, keeping D slots in flight.
+// res / vf, issuing the loads of D slots at a time before adding them.
 template <int NS, int D = (NS <= 3 ? 8 : 2)>
 __device__ __forceinline__ void sum_slot_tail(const double *slots, int par, int ntiles,
                                               double (&res)[kNP], float (&vf)[2]) {
-  int t = (int)threadIdx.x + kBlock;
-  for (; t + (D - 1) * kBlock < ntiles; t += D * kBlock) {
+  for (int base = (int)threadIdx.x + kBlock; base < ntiles; base += D * kBlock) {
     double buf[D][NS];
 #pragma unroll
-    for (int u = 0; u < D; ++u)
+    for (int u = 0; u < D; ++u) {
+      const int t = base + u * kBlock;
 #pragma unroll
-      for (int k = 0; k < NS; ++k) buf[u][k] = slots[slot_index(t + u * kBlock, par, k)];
+      for (int k = 0; k < NS; ++k) buf[u][k] = t < ntiles ? slots[slot_index(t, par, k)] : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < D; ++u) {
+      if (base + u * kBlock < ntiles) {
 #pragma unroll
-      for (int k = 0; k < NS; ++k) res[k] += buf[u][k];
-      vf[0] += (float)buf[u][0];
-      vf[1] += (float)buf[u][1];
+        for (int k = 0; k < NS; ++k) res[k] += buf[u][k];
+        vf[0] += (float)buf[u][0];
+        vf[1] += (float)buf[u][1];
+      }
     }
-  }
-  for (; t < ntiles; t += kBlock) {
-    double v[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) v[k] = slots[slot_index(t, par, k)];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) res[k] += v[k];
-    vf[0] += (float)v[0];
-    vf[1] += (float)v[1];
   }
 }
 
@@ -346,9 +340,9 @@ __device__ __forceinline__ void sum_partials(const double *slots, int par, int n
   vf[0] = mine ? (float)pf[0] : 0.0f;
   vf[1] = mine ? (float)pf[1] : 0.0f;
   if (ntiles > kBlock) {
-    if (ns == 2) sum_slot_tail<2, DEEP ? 16 : 8>(slots, par, ntiles, res, vf);
-    else if (ns == 3) sum_slot_tail<3, DEEP ? 12 : 8>(slots, par, ntiles, res, vf);
-    else sum_slot_tail<kNP, DEEP ? 4 : 2>(slots, par, ntiles, res, vf);
+    if (ns == 2) sum_slot_tail<2, DEEP ? 40 : 4>(slots, par, ntiles, res, vf);
+    else if (ns == 3) sum_slot_tail<3, DEEP ? 24 : 4>(slots, par, ntiles, res, vf);
+    else sum_slot_tail<kNP, DEEP ? 8 : 2>(slots, par, ntiles, res, vf);
   }
   block_slots(ns, f32, res, vf);
 }

@@ -50,6 +50,20 @@ def test_batch_equals_alone(mode, mixed):
             assert st[k] == sa[k], (inst.name, k)
 
 
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_batch_equals_alone_many_tiles(mixed):
+    """Members with more tiles than threads per workgroup (their slot sums
+    have tails): the batch (split form) equals each one alone (fused form)."""
+    insts = [instances.obstacle(300, 4, amplitude=0.4), instances.varcoef(270, 1),
+             instances.obstacle(45, 2)]
+    xs, stats = _batch(insts, 0, precision=mixed)
+    for inst, x, st in zip(insts, xs, stats):
+        xa, ga, sa = solo(inst, precision=mixed)
+        assert st["status"] == sa["status"] == 0, (st, sa)
+        assert np.array_equal(x, xa), inst.name
+        assert st["cg_iters"] == sa["cg_iters"], inst.name
+
+
 def test_batch_matches_oracle():
     insts = mix(5, seed=3)
     xs, stats = _batch(insts, 1, tol_rel=1e-12)

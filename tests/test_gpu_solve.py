@@ -145,7 +145,8 @@ def test_deterministic_and_graph_invariant():
         assert s1[k] == s2[k] == s3[k], k
 
 
-@pytest.mark.parametrize("case", ["c0", "c0_csr", "c1s", "ragged_mixed", "ragged_csr_mixed"])
+@pytest.mark.parametrize("case", ["c0", "c0_csr", "c1s", "ragged_mixed", "ragged_csr_mixed",
+                                  "many_tiles", "many_tiles_mixed"])
 def test_fused_and_split_forms_agree_bitwise(case):
     """The two launch forms use the same tiles and summation orders."""
     import paper_cs_0101018_amd as gpcg
@@ -155,6 +156,9 @@ def test_fused_and_split_forms_agree_bitwise(case):
         "c1s": (instances.varcoef(96, 3), None, gpcg.GPCG_PREC_FP64),
         "ragged_mixed": (instances.obstacle(77, 5), None, gpcg.GPCG_PREC_MIXED),
         "ragged_csr_mixed": (instances.obstacle(77, 5), "csr", gpcg.GPCG_PREC_MIXED),
+        # more tiles than threads per workgroup: every slot sum has a tail
+        "many_tiles": (instances.obstacle(601, 1), None, gpcg.GPCG_PREC_FP64),
+        "many_tiles_mixed": (instances.varcoef(333, 2), None, gpcg.GPCG_PREC_MIXED),
     }[case]
     res = [G.solve(inst, kind, precision=prec, form=f)
            for f in (gpcg.GPCG_FORM_FUSED, gpcg.GPCG_FORM_SPLIT)]
