@@ -779,6 +779,18 @@ __device__ __forceinline__ void advance(const QPStatic *S, QPDyn &sd, const doub
 
 // --------------------------------------------------------- state transfer
 
+// The read-only part of a QP's state is copied into LDS with the dynamic
+// part (by the top threads of the workgroup, in parallel), so the transition
+// and the passes read options and array pointers without a global round trip.
+constexpr int kStaticWords = (int)(sizeof(QPStatic) / 4);
+static_assert(sizeof(QPStatic) % 4 == 0 && kStaticWords <= kBlock, "QPStatic copy");
+
+__device__ __forceinline__ void copy_static(const QPStatic *src, QPStatic *dst) {
+  const int w = (int)threadIdx.x - (kBlock - kStaticWords);
+  if (w >= 0)
+    reinterpret_cast<uint32_t *>(dst)[w] = reinterpret_cast<const uint32_t *>(src)[w];
+}
+
 constexpr int kDynWords = (int)(sizeof(QPDyn) / 4);
 static_assert(sizeof(QPDyn) % 8 == 0, "QPDyn must be a whole number of words");
 static_assert(kDynWords <= kBlock, "QPDyn must fit one word per thread");
@@ -903,24 +915,26 @@ __device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCo
 template <typename CT, bool SPEC>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
+  __shared__ QPStatic ss;
   __shared__ int s_fresh_done;
   // the fused form runs one QP (L.single); workgroup = tile
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   QPDev *q = L.single;
-  const QPStatic *S = &q->st;
   const int par = L.parity;
   double *slots = tile_slots(q);
   double pf[kNP];
   prefetch_slot(slots, par, pf);  // issued together with the state load
-  const int ntiles = S->ntiles, mixed = S->mixed;
   const uint64_t clk = wall_clock64();
   // SPEC launches hold only stencil QPs with one unknown per thread
   const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
-  const bool own = SPEC && kk < S->n;
+  const bool own = SPEC && kk < q->st.n;
   CGOperands<CT> P{};
-  if (own) cg_prefetch<CT>(S, par, kk, P);
+  if (own) cg_prefetch<CT>(&q->st, par, kk, P);
   copy_dyn(&q->dyn[par], &sd);
+  copy_static(&q->st, &ss);
   __syncthreads();
+  const QPStatic *S = &ss;
+  const int ntiles = S->ntiles, mixed = S->mixed;
   if (sd.c.pending) {
     double R[kNP];
     sum_partials(slots, par, ntiles, sd.c.phase, f32_slots(mixed, sd.c.phase), pf, R);
@@ -977,16 +991,18 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
 // One workgroup per QP of the launch (L.single: grid 1; else grid nqp, QP b).
 __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
+  __shared__ QPStatic ss;
   __shared__ int s_fresh_done;
   QPDev *q = L.single ? L.single : L.qps[blockIdx.x];
-  const QPStatic *S = &q->st;
   const int par = L.parity;
   const double *slots = tile_slots(q);
   double pf[kNP];
   prefetch_slot(slots, par, pf);
   const uint64_t clk = wall_clock64();
   copy_dyn(&q->dyn[par], &sd);
+  copy_static(&q->st, &ss);
   __syncthreads();
+  const QPStatic *S = &ss;
   if (sd.c.pending) {
     double R[kNP];
     sum_partials<true>(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
@@ -1019,6 +1035,7 @@ static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 template <typename CT, bool SPEC>
 __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
+  __shared__ QPStatic ss;
   const int wg = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   QPDev *q;
   int t0, nt;
@@ -1032,16 +1049,17 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     t0 = it.tile0;
     nt = it.ntile;
   }
-  const QPStatic *S = &q->st;
   const int par = L.parity;
   int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
-  bool own = kk < S->n;
+  bool own = kk < q->st.n;
   CGOperands<CT> P{};
-  if (SPEC && own) cg_prefetch<CT>(S, par, kk, P);
+  if (SPEC && own) cg_prefetch<CT>(&q->st, par, kk, P);
   if (threadIdx.x < kCoreWords)
     reinterpret_cast<uint32_t *>(&sc)[threadIdx.x] =
         reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c)[threadIdx.x];
+  copy_static(&q->st, &ss);
   __syncthreads();
+  const QPStatic *S = &ss;
   const int phase = sc.phase;
   if (phase == PH_DONE) return;
   const int mixed = S->mixed, ntiles = S->ntiles;
