@@ -393,6 +393,9 @@ def main():
                     help="launch form of single-QP workloads")
     ap.add_argument("--tiles-per-wg", type=int, default=0,
                     help="split form: consecutive tiles per data workgroup (0 = library default)")
+    ap.add_argument("--prefetch", default="auto", choices=["auto", "on", "off"],
+                    help="early CG operand loads (stencil QPs)")
+    ap.add_argument("--chunk", type=int, default=0, help="passes per graph replay (0 = default)")
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
                     help="free set of the reduced CG: byte mask or compacted list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -446,8 +449,10 @@ def main():
     form = {"auto": gpcg.GPCG_FORM_AUTO, "fused": gpcg.GPCG_FORM_FUSED,
             "split": gpcg.GPCG_FORM_SPLIT}[args.form]
     fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
-    solver = gpcg.Solver(op, device=dev, form=form, free_set=fs,
-                         tiles_per_wg=args.tiles_per_wg, **opts)
+    pf = {"auto": gpcg.GPCG_PREFETCH_AUTO, "on": gpcg.GPCG_PREFETCH_ON,
+          "off": gpcg.GPCG_PREFETCH_OFF}[args.prefetch]
+    solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf,
+                         tiles_per_wg=args.tiles_per_wg, chunk=args.chunk, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
 
@@ -456,7 +461,8 @@ def main():
         return solver.solve(b, l, u, x)
 
     tuned = None
-    if not args.no_autotune and args.form == "auto" and args.tiles_per_wg == 0:
+    if (not args.no_autotune and args.form == "auto" and args.tiles_per_wg == 0
+            and args.prefetch == "auto" and args.chunk == 0):
         tuned = solver.autotune(b, l, u, x0)["chosen"]
         log(f"autotune: {tuned}")
     for _ in range(args.warmup):
@@ -484,13 +490,21 @@ def main():
     achieved = bytes_per_launch / avg_launch_s / 1e9
     solves_per_s = args.steps / wall
     ntiles = -(-inst.n // 256)
-    fused = args.form == "fused" or (args.form == "auto" and ntiles <= 1024)
-    if fused:
-        kname, ksub = "gpcg::step_kernel (one fused GPCG pass per launch)", "step_kernel"
+    if tuned is not None:
+        fused = tuned["form"] == gpcg.GPCG_FORM_FUSED
+        prefetch = bool(tuned["prefetch"])
     else:
-        kname = ("gpcg::pass_kernel (data kernel of the split form; the time per launch "
-                 "is that of one transition + data kernel pair)")
-        ksub = "pass_kernel"
+        fused = args.form == "fused" or (args.form == "auto" and ntiles <= 1024)
+        prefetch = args.prefetch != "off"
+    ct = "float" if opts.get("precision") else "double"
+    variant = f"<{ct}, {'true' if prefetch else 'false'}>"
+    if fused:
+        kname = f"gpcg::step_kernel{variant} (one fused GPCG pass per launch)"
+        ksub = f"step_kernel{variant}"
+    else:
+        kname = (f"gpcg::pass_kernel{variant} (data kernel of the split form; the time per "
+                 "launch is that of one transition + data kernel pair)")
+        ksub = f"pass_kernel{variant}"
     traffic = traffic_from_profile(args.workload, ksub)
 
     res = {
@@ -508,7 +522,8 @@ def main():
         "data": "synthetic (seeded instance generator, seed 0)",
         "config": {"workload": args.workload, "description": desc, "n": inst.n,
                    "free_set": args.free_set, "form": args.form,
-                   "tiles_per_wg": args.tiles_per_wg,
+                   "tiles_per_wg": args.tiles_per_wg, "prefetch": args.prefetch,
+                   "chunk": args.chunk,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
         "roofline": {

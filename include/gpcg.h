@@ -119,7 +119,14 @@ typedef struct {
   int32_t tiles_per_wg; /* split form: consecutive 256-unknown tiles per data
                           workgroup, 1..64; 0 = 1.  The answer does not
                           depend on it                                        */
+  int32_t prefetch;     /* CG operands of stencil QPs loaded before the state
+                          is read: GPCG_PREFETCH_AUTO (on), _ON or _OFF.  The
+                          answer does not depend on it                        */
 } gpcg_options;
+
+#define GPCG_PREFETCH_AUTO 0
+#define GPCG_PREFETCH_ON 1
+#define GPCG_PREFETCH_OFF 2
 
 #define GPCG_FORM_AUTO 0
 #define GPCG_FORM_FUSED 1 /* one launch per pass; every workgroup folds the
@@ -130,7 +137,7 @@ typedef struct {
 /* Fills the defaults: tol_rel 1e-8, tol_abs 0, eta1 0.1, eta2 0.05,
  * eta2_reduce 0.1, mu 0.01, max_outer 100000, max_gp 50, max_backtrack 60,
  * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
- * form GPCG_FORM_AUTO. */
+ * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO. */
 void gpcg_options_default(gpcg_options *opt);
 
 /* ------------------------------------------------------------------- stats */
@@ -212,8 +219,8 @@ int gpcg_projected_gradient(gpcg_handle h, const double *x, const double *l, con
  * the same answer; a candidate whose answer differs is never kept and makes
  * the call return GPCG_ERR_HIP.  The winner is kept by the handle and in a
  * process-wide table keyed by operator shape, precision and free-set form:
- * handles created later with GPCG_FORM_AUTO, tiles_per_wg 0 and chunk 0 start
- * from it.  x0 is read only; x_work (device, n doubles) receives the answer.
+ * handles created later with GPCG_FORM_AUTO, tiles_per_wg 0, chunk 0 and
+ * GPCG_PREFETCH_AUTO start from it.  x0 is read only; x_work (device, n doubles) receives the answer.
  * report: NULL or filled with every candidate timed and the choice. */
 #define GPCG_TUNE_MAX 32
 

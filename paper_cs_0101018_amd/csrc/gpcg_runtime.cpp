@@ -103,6 +103,8 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "unknown launch form");
   if (o->tiles_per_wg < 0 || o->tiles_per_wg > 64)
     return fail(GPCG_ERR_ARG, "tiles_per_wg must be in [0, 64]");
+  if (o->prefetch < GPCG_PREFETCH_AUTO || o->prefetch > GPCG_PREFETCH_OFF)
+    return fail(GPCG_ERR_ARG, "unknown prefetch mode");
   return GPCG_OK;
 }
 
@@ -550,6 +552,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->max_stall = 25;
   o->form = GPCG_FORM_AUTO;
   o->tiles_per_wg = 0;
+  o->prefetch = GPCG_PREFETCH_AUTO;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {
@@ -604,9 +607,10 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   h->cfg.split = o.form == GPCG_FORM_SPLIT ||
                  (o.form == GPCG_FORM_AUTO && h->L.ntiles > kFusedMaxTiles);
   h->cfg.tiles_per_wg = o.tiles_per_wg > 0 ? o.tiles_per_wg : 1;
-  h->cfg.spec = spec_ok(h->st) ? 1 : 0;
+  h->cfg.spec = spec_ok(h->st) && o.prefetch != GPCG_PREFETCH_OFF ? 1 : 0;
   h->cfg.chunk = default_chunk(o);
-  if (o.form == GPCG_FORM_AUTO && o.tiles_per_wg == 0 && o.chunk == 0) {
+  if (o.form == GPCG_FORM_AUTO && o.tiles_per_wg == 0 && o.chunk == 0 &&
+      o.prefetch == GPCG_PREFETCH_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(h));
     if (it != g_tuned.end()) h->cfg = it->second;
