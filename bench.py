@@ -45,6 +45,8 @@ WORKLOADS = {
     "obstacle1024_mixed": ("obstacle_ub_1024", dict(precision=1), "GPCG mixed, obstacle 1024x1024"),
     "obstacle1600_fp64": ("obstacle_ub_1600", dict(), "GPCG FP64, obstacle 1600x1600"),
     "obstacle1600_mixed": ("obstacle_ub_1600", dict(precision=1), "GPCG mixed, obstacle 1600x1600"),
+    "bearing256_fp64": ("bearing256", dict(), "GPCG FP64, -div(c grad u) 256x256, "
+                        "c=(1+0.9 cos 2 pi s)^3 (eccentricity 0.9), l=0, u=inf, tol 1e-8 rel"),
 }
 BATCH_WORKLOADS = ("batch512_fp64", "batch512_mixed")
 SERVE_WORKLOADS = ("serve4096",)
@@ -150,6 +152,8 @@ def make_instance(key):
         return instances.obstacle50(0)
     if key == "varcoef256":
         return instances.varcoef256(0)
+    if key == "bearing256":
+        return instances.varcoef(256, 0, eps=0.9, name="bearing256")
     if key.startswith("obstacle_ub_"):
         return instances.obstacle_ub(int(key.split("_")[-1]), 0)
     raise KeyError(key)
@@ -159,7 +163,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(inst, budget_s=12.0):
+def cpu_baseline(inst, budget_s=12.0, precond=0):
     """The FP64 oracle, as it stands, on this host: solves/sec on a bounded
     sample (whole solves of the same workload until the budget is spent)."""
     import oracle
@@ -168,7 +172,7 @@ def cpu_baseline(inst, budget_s=12.0):
     t0 = time.perf_counter()
     k = 0
     while True:
-        ora.gpcg(csr, inst.b, inst.l, inst.u, inst.x0)
+        ora.gpcg(csr, inst.b, inst.l, inst.u, inst.x0, precond=precond)
         k += 1
         el = time.perf_counter() - t0
         if el >= budget_s or k >= 200:
@@ -207,9 +211,20 @@ def spmv_extras(gpcg, torch, dev, reps=40):
                 e1.record()
                 torch.cuda.synchronize()
                 t = e0.elapsed_time(e1) * 1e-3 / reps
+                # the same bytes moved by a device copy (read + write), same cycling
+                e0.record()
+                for i in range(reps):
+                    a_, b_, _ = sets[i % nsets]
+                    b_.copy_(a_)
+                e1.record()
+                torch.cuda.synchronize()
+                tc = e0.elapsed_time(e1) * 1e-3 / reps
+                copy_gbs = 2 * sets[0][0].numel() * sets[0][0].element_size() / tc / 1e9
                 key = f"spmv_const{N}_{'fp32' if prec else 'fp64'}_{'cold' if cold else 'warm'}"
                 out[key] = dict(GBs=round(set_bytes / t / 1e9, 1), us=round(t * 1e6, 2),
-                                bytes_per_var=per, frac=round(set_bytes / t / 1e9 / HBM_PEAK_GBS, 3))
+                                bytes_per_var=per, frac=round(set_bytes / t / 1e9 / HBM_PEAK_GBS, 3),
+                                copy_GBs=round(copy_gbs, 1),
+                                frac_of_copy=round(set_bytes / t / 1e9 / copy_gbs, 3))
                 del sets
             s.close()
     return out
@@ -235,7 +250,9 @@ def bench_batch(args, gpcg, torch, dev):
     data = [_dev_instance(i, gpcg, torch, dev) for i in insts]
     mode = gpcg.GPCG_BATCH_PERSISTENT if args.batch_mode == "persistent" else gpcg.GPCG_BATCH_STEPPED
     fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
-    solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed), free_set=fs) for d in data]
+    pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
+    solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed), free_set=fs, precond=pc)
+               for d in data]
     batch = gpcg.Batch(solvers, device=dev)
     xs = [torch.empty_like(d[4]) for d in data]
     probs = [(d[1], d[2], d[3], x) for d, x in zip(data, xs)]
@@ -270,7 +287,8 @@ def bench_batch(args, gpcg, torch, dev):
         "data": "synthetic (512 obstacle / variable-coefficient QPs, sides log-uniform "
                 "in [32, 384], seed 0)",
         "config": {"workload": args.workload, "qps": len(insts), "unknowns": n_tot,
-                   "batch_mode": args.batch_mode, "free_set": args.free_set},
+                   "batch_mode": args.batch_mode, "free_set": args.free_set,
+                   "precond": args.precond},
         "roofline": {"bound": "hbm", "kernel": "whole batch (every pass of every QP)",
                      "achieved": round(alg_bytes / wall / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg_bytes / wall / 1e9 / HBM_PEAK_GBS, 4),
@@ -396,6 +414,8 @@ def main():
     ap.add_argument("--prefetch", default="auto", choices=["auto", "on", "off"],
                     help="early CG operand loads (stencil QPs)")
     ap.add_argument("--chunk", type=int, default=0, help="passes per graph replay (0 = default)")
+    ap.add_argument("--precond", default="none", choices=["none", "jacobi"],
+                    help="preconditioner of the reduced CG")
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
                     help="free set of the reduced CG: byte mask or compacted list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -451,7 +471,8 @@ def main():
     fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
     pf = {"auto": gpcg.GPCG_PREFETCH_AUTO, "on": gpcg.GPCG_PREFETCH_ON,
           "off": gpcg.GPCG_PREFETCH_OFF}[args.prefetch]
-    solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf,
+    pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
+    solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf, precond=pc,
                          tiles_per_wg=args.tiles_per_wg, chunk=args.chunk, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
@@ -497,7 +518,8 @@ def main():
         fused = args.form == "fused" or (args.form == "auto" and ntiles <= 1024)
         prefetch = args.prefetch != "off"
     ct = "float" if opts.get("precision") else "double"
-    variant = f"<{ct}, {'true' if prefetch else 'false'}>"
+    variant = (f"<{ct}, {'true' if prefetch else 'false'}, "
+               f"{'true' if args.precond == 'jacobi' else 'false'}>")
     if fused:
         kname = f"gpcg::step_kernel{variant} (one fused GPCG pass per launch)"
         ksub = f"step_kernel{variant}"
@@ -523,6 +545,7 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n": inst.n,
                    "free_set": args.free_set, "form": args.form,
                    "tiles_per_wg": args.tiles_per_wg, "prefetch": args.prefetch,
+                   "precond": args.precond,
                    "chunk": args.chunk,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
@@ -548,7 +571,7 @@ def main():
         res["extras"] = spmv_extras(gpcg, torch, dev)
     solver.close()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inst)
+        res["cpu_baseline"] = cpu_baseline(inst, precond=int(args.precond == "jacobi"))
     print(json.dumps(res), flush=True)
 
 

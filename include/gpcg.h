@@ -122,7 +122,17 @@ typedef struct {
   int32_t prefetch;     /* CG operands of stencil QPs loaded before the state
                           is read: GPCG_PREFETCH_AUTO (on), _ON or _OFF.  The
                           answer does not depend on it                        */
+  int32_t precond;      /* preconditioner of the reduced CG: GPCG_PRECOND_NONE
+                          or GPCG_PRECOND_JACOBI (the diagonal of the reduced
+                          Hessian A_k, i.e. of A on the free set; Section
+                          "Preconditioners" of the paper).  x* is the same;
+                          the CG iterates and counts are not.  The constant
+                          stencil has a constant diagonal, which leaves the
+                          iterates unchanged: there it is not applied      */
 } gpcg_options;
+
+#define GPCG_PRECOND_NONE 0
+#define GPCG_PRECOND_JACOBI 1
 
 #define GPCG_PREFETCH_AUTO 0
 #define GPCG_PREFETCH_ON 1
@@ -137,7 +147,8 @@ typedef struct {
 /* Fills the defaults: tol_rel 1e-8, tol_abs 0, eta1 0.1, eta2 0.05,
  * eta2_reduce 0.1, mu 0.01, max_outer 100000, max_gp 50, max_backtrack 60,
  * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
- * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO. */
+ * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO,
+ * precond GPCG_PRECOND_NONE. */
 void gpcg_options_default(gpcg_options *opt);
 
 /* ------------------------------------------------------------------- stats */

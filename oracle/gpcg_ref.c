@@ -43,7 +43,11 @@
  *    the solve stops as stagnated when ||P grad q|| after a projected search
  *    has not improved on its best value for max_stall consecutive searches;
  *  - decreases of q are evaluated as g's + 1/2 s'As (equal to q(x+s)-q(x)) and
- *    the CG decrease as 1/2 alpha_j rho'rho (equal to q_k(w_{j-1})-q_k(w_j)).
+ *    the CG decrease as 1/2 alpha_j rho'z, z = M^{-1} rho (equal to
+ *    q_k(w_{j-1})-q_k(w_j));
+ *  - the reduced CG may be preconditioned by the diagonal of A_k (the point
+ *    Jacobi preconditioner of the paper's Section "Preconditioners"); the
+ *    default is no preconditioner.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
  * round-to-nearest, sequential sums in index order).
@@ -78,6 +82,7 @@ typedef struct {
   double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
   int32_t max_outer, max_gp, max_backtrack, max_cg; /* max_cg <= 0: m_k */
   int32_t max_stall; /* outer iterations without a new best ||P grad q|| */
+  int32_t precond;   /* reduced CG: 0 none, 1 diagonal (Jacobi) of A_k */
 } ora_options;
 
 typedef struct {
@@ -103,6 +108,7 @@ void ora_default_options(ora_options *o) {
   o->max_backtrack = 60;
   o->max_cg = 0;
   o->max_stall = 25;
+  o->precond = 0;
 }
 
 /* ----------------------------------------------------------- building blocks */
@@ -302,8 +308,8 @@ static void extract_submatrix(const ora_csr *A, const int64_t *F, int64_t m, con
  * ORA_ERR_NOT_SPD; *iters gets the number of CG iterations; decs (optional,
  * capacity dec_cap) receives q_k(w_{j-1}) - q_k(w_j) for each iteration. */
 int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const double *g,
-                   double eta, int32_t max_cg, double *d, int32_t *iters, double *decs,
-                   int32_t dec_cap) {
+                   double eta, int32_t max_cg, int32_t precond, double *d, int32_t *iters,
+                   double *decs, int32_t dec_cap) {
   int64_t n = A->n;
   int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
@@ -330,8 +336,23 @@ int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const doubl
 
   double *w = (double *)calloc((size_t)m, sizeof(double));
   double *rho = (double *)malloc(sizeof(double) * (size_t)m);
+  double *z = (double *)malloc(sizeof(double) * (size_t)m);
   double *p = (double *)malloc(sizeof(double) * (size_t)m);
   double *q = (double *)malloc(sizeof(double) * (size_t)m);
+  double *dinv = (double *)malloc(sizeof(double) * (size_t)m);
+  int status = ORA_OK;
+  /* Preconditioner M: the identity, or the diagonal of A_k (the paper's
+   * diagonal Jacobi preconditioner, Section "Preconditioners"). */
+  for (int64_t a = 0; a < m; ++a) {
+    dinv[a] = 1.0;
+    if (precond == 1) {
+      double diag = 0.0;
+      for (int32_t e = rp[a]; e < rp[a + 1]; ++e)
+        if (ci[e] == a) diag += va[e];
+      if (!(diag > 0.0)) status = ORA_ERR_NOT_SPD;
+      dinv[a] = 1.0 / diag;
+    }
+  }
   /* r_k = Z_k' grad q(x_k); the residual of A_k w + r_k = 0 at w = 0 is -r_k */
   for (int64_t a = 0; a < m; ++a) {
 #if ORA_MUTANT == 6
@@ -339,14 +360,14 @@ int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const doubl
 #else
     rho[a] = -g[F[a]];
 #endif
-    p[a] = rho[a];
+    z[a] = precond == 1 ? dinv[a] * rho[a] : rho[a];
+    p[a] = z[a];
   }
-  double rr = ora_dot(m, rho, rho);
+  double rz = ora_dot(m, rho, z);
   int64_t cap = max_cg > 0 ? max_cg : m;
   double decmax = -INFINITY;
-  int status = ORA_OK;
   int32_t j = 0;
-  if (rr > 0.0) {
+  if (status == ORA_OK && rz > 0.0) {
     for (;;) {
       ora_matvec(&Ak, p, q);
       double pq = ora_dot(m, p, q);
@@ -354,35 +375,44 @@ int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const doubl
         status = ORA_ERR_NOT_SPD;
         break;
       }
-      double alpha = rr / pq;
+      double alpha = rz / pq;
       for (int64_t a = 0; a < m; ++a) w[a] += alpha * p[a];
       for (int64_t a = 0; a < m; ++a) rho[a] -= alpha * q[a];
-      double rr_new = ora_dot(m, rho, rho);
+      for (int64_t a = 0; a < m; ++a) z[a] = precond == 1 ? dinv[a] * rho[a] : rho[a];
+      double rz_new = ora_dot(m, rho, z);
       ++j;
+      /* q_k(w_{j-1}) - q_k(w_j) = alpha rho'z - 1/2 alpha^2 p'A_k p = 1/2 alpha rho'z,
+       * since rho'p = rho'z for (preconditioned) conjugate gradients */
 #if ORA_MUTANT == 10
-      double dec = alpha * rr;
+      double dec = alpha * rz;
 #else
-      double dec = 0.5 * alpha * rr; /* q_k(w_{j-1}) - q_k(w_j) */
+      double dec = 0.5 * alpha * rz;
 #endif
       if (decs && j <= dec_cap) decs[j - 1] = dec;
-      int stop = (rr_new == 0.0) || (j >= 2 && dec <= eta * decmax) || (j >= cap);
+      int stop = (rz_new == 0.0) || (j >= 2 && dec <= eta * decmax) || (j >= cap);
       if (dec > decmax) decmax = dec;
       if (stop) break;
 #if ORA_MUTANT == 5
-      double beta = rr / rr_new;
+      double beta = rz / rz_new;
 #else
-      double beta = rr_new / rr;
+      double beta = rz_new / rz;
 #endif
+#if ORA_MUTANT == 11
       for (int64_t a = 0; a < m; ++a) p[a] = rho[a] + beta * p[a];
-      rr = rr_new;
+#else
+      for (int64_t a = 0; a < m; ++a) p[a] = z[a] + beta * p[a];
+#endif
+      rz = rz_new;
     }
   }
   for (int64_t a = 0; a < m; ++a) d[F[a]] = w[a];
   *iters = j;
   free(w);
   free(rho);
+  free(z);
   free(p);
   free(q);
+  free(dinv);
   free(rp);
   free(ci);
   free(va);
@@ -527,7 +557,7 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
         break;
       }
       int32_t it = 0;
-      int cgs = ora_reduced_cg(A, fm, g, eta, opt.max_cg, d, &it, NULL, 0);
+      int cgs = ora_reduced_cg(A, fm, g, eta, opt.max_cg, opt.precond, d, &it, NULL, 0);
       st->cg_iters += it;
       ++st->cg_phases;
       if (cgs != ORA_OK) {

@@ -60,6 +60,7 @@ struct QPStatic {
   void *pv, *wv;                 // CG direction and iterate
   uint8_t *mask;                 // free set of the current CG phase
   int32_t *list;                 // list form: free indices in ascending order (else null)
+  const void *dinv;              // Jacobi preconditioner: 1 / diag(A) (FP64/FP32), or null
   int32_t *host_flag;            // device view of a mapped host word, or null
   double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
 };
@@ -136,13 +137,20 @@ struct PersistLaunch {
   int32_t nqp;
   int32_t wg_total;
   int64_t spin_limit;        // polls before a wait is declared hung
+  int32_t pre;               // some QP has the Jacobi preconditioner
+  int32_t pad;
 };
+
+// Kernel variants (the `spec` argument of the launchers below is a set of
+// these bits).  kVarSpec: the launch holds only stencil QPs with 256-unknown
+// tiles, which may load CG operands before the state is known.  kVarPre: some
+// QP of the launch has the Jacobi preconditioner.
+constexpr int kVarSpec = 1;
+constexpr int kVarPre = 2;
 
 }  // namespace gpcg
 
 extern "C++" {
-// spec: the launch holds only stencil QPs with 256-unknown tiles, which may use
-// the variant that loads CG operands before the state is known.
 void *gpcg_step_kernel_ptr(int mixed, int spec);
 int gpcg_launch_step(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
 // Split form: a transition kernel (grid = QPs) then a data kernel (grid = tiles).
@@ -154,6 +162,9 @@ int gpcg_launch_spmv(const gpcg::QPDev *dqp, int64_t n, const void *v, void *y,
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
                       const double *g, double *pg, double *part, double *out4, void *stream);
 int gpcg_launch_convert_f32(const double *src, float *dst, int64_t count, void *stream);
+// 1 / diag(A) of the QP's operator into dinv (FP64 or FP32); the device state
+// must hold the operator.  Returns -1 on a launch error.
+int gpcg_launch_diag_inv(const gpcg::QPDev *dqp, void *dinv, int f32, void *stream);
 int gpcg_persistent_max_blocks(int mixed, int *blocks_per_cu);
 int gpcg_launch_persistent(const gpcg::PersistLaunch &P, int grid, int mixed, void *stream);
 }

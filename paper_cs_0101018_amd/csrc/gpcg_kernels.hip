@@ -364,7 +364,7 @@ __device__ __forceinline__ void face_acc(double x, double l, double u, double g,
 // One pass over the unknowns [k0, k1) of a tile (the list entries [k0, k1)
 // for a CG iteration of the list form).  `slots` are the QP's tile slots: the
 // list pass reads the free counts the set-up pass left at parity lpar.
-template <typename CT>
+template <typename CT, bool PRE>
 __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restrict__ slots,
                          const QPCore &d, int phase, int lpar, int64_t k0, int64_t k1,
                          double (&acc)[kNP], float (&accf)[2]) {
@@ -444,9 +444,12 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       CT *__restrict__ s1 = (CT *)S->sq[1];
       CT *__restrict__ p = (CT *)S->pv;
       CT *__restrict__ w = (CT *)S->wv;
-      auto rv = [&](int64_t j) {
+      // preconditioned residual z = D^-1 rho (rho itself without a preconditioner)
+      const CT *__restrict__ dinv = PRE ? (const CT *)S->dinv : nullptr;
+      auto zv = [&](int64_t j) {
         const double xj = x[j];
-        return (l[j] < xj && xj < u[j]) ? (CT)(-g[j]) : CT(0);
+        const CT r = (l[j] < xj && xj < u[j]) ? (CT)(-g[j]) : CT(0);
+        return dinv ? r * dinv[j] : r;
       };
       for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
         const double xk = x[k];
@@ -454,16 +457,17 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
         mask[k] = fr ? 1 : 0;
         if (fr) {
           const CT rk = (CT)(-g[k]);
-          const CT uk = apply_row<CT>(A, k, rv);
+          const CT zk = dinv ? rk * dinv[k] : rk;
+          const CT uk = apply_row<CT>(A, k, zv);  // A z
           r0[k] = rk;
           u0[k] = uk;
           w[k] = CT(0);
           if (sizeof(CT) == 4) {
-            accf[0] = fmaT<float>((float)rk, (float)rk, accf[0]);
-            accf[1] = fmaT<float>((float)rk, (float)uk, accf[1]);
+            accf[0] = fmaT<float>((float)rk, (float)zk, accf[0]);
+            accf[1] = fmaT<float>((float)zk, (float)uk, accf[1]);
           } else {
-            acc[0] = __fma_rn((double)rk, (double)rk, acc[0]);
-            acc[1] = __fma_rn((double)rk, (double)uk, acc[1]);
+            acc[0] = __fma_rn((double)rk, (double)zk, acc[0]);
+            acc[1] = __fma_rn((double)zk, (double)uk, acc[1]);
           }
           acc[2] += 1.0;
         } else {
@@ -518,6 +522,12 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i
       auto snew = [&](int64_t j) { return first ? uo[j] : fmaT<CT>(be, so[j], uo[j]); };
       auto rnew = [&](int64_t j) { return fmaT<CT>(-al, snew(j), ro[j]); };
+      // z = D^-1 rho with the Jacobi preconditioner, else rho; u = A z
+      const CT *__restrict__ dinv = PRE ? (const CT *)S->dinv : nullptr;
+      auto znew = [&](int64_t j) {
+        const CT r = rnew(j);
+        return dinv ? r * dinv[j] : r;
+      };
       CT gam = CT(0), del = CT(0);
       const int32_t *__restrict__ list = S->list;
       // list form: entries [k0, k1) of the free list; mask form: rows [k0, k1)
@@ -529,15 +539,18 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
         const CT rk = ro[k];
         const CT sk = snew(k);
         const CT r1 = fmaT<CT>(-al, sk, rk);
-        const CT pk = first ? rk : fmaT<CT>(be, p[k], rk);
+        const CT dk = dinv ? dinv[k] : CT(1);
+        const CT zk = dinv ? rk * dk : rk;
+        const CT z1 = dinv ? r1 * dk : r1;
+        const CT pk = first ? zk : fmaT<CT>(be, p[k], zk);
         w[k] = fmaT<CT>(al, pk, w[k]);
         p[k] = pk;
         sn[k] = sk;
         rn[k] = r1;
-        const CT u1 = apply_row<CT>(A, k, rnew);
+        const CT u1 = apply_row<CT>(A, k, znew);
         un[k] = u1;
-        gam = fmaT<CT>(r1, r1, gam);
-        del = fmaT<CT>(r1, u1, del);
+        gam = fmaT<CT>(r1, z1, gam);
+        del = fmaT<CT>(z1, u1, del);
       }
       if (sizeof(CT) == 4) {
         accf[0] = (float)gam;
@@ -816,6 +829,7 @@ struct CGOperands {
   CT rN, uN, sN;       // and at the north neighbour k + nx
   CT rX, uX, sX;       // first / last thread of the tile: at k - 1 / k + 1 (0 otherwise)
   CT wt[4];            // edge weights W, E, S, N (variable stencil)
+  CT dk, dS, dN, dX;   // Jacobi preconditioner 1 / diag(A) at k, k - nx, k + nx, the outside row
   int m;               // free-set mask at k
   bool hasW, hasE, hasS, hasN;
 };
@@ -824,7 +838,7 @@ struct CGOperands {
 // consecutive unknowns.  The west and east neighbours are the neighbouring
 // threads of the tile (exchanged through LDS after the update); only the
 // first and last threads load the row outside the tile.
-template <typename CT>
+template <typename CT, bool PRE>
 __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t k,
                                             CGOperands<CT> &P) {
   const OpView<CT> A = op_view<CT>(S);
@@ -856,6 +870,13 @@ __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t
   P.rX = kx >= 0 ? ro[kx] : CT(0);
   P.uX = kx >= 0 ? uo[kx] : CT(0);
   P.sX = kx >= 0 ? so[kx] : CT(0);
+  const CT *__restrict__ dinv = PRE ? (const CT *)S->dinv : nullptr;
+  if (dinv) {
+    P.dk = dinv[k];
+    P.dS = P.hasS ? dinv[k - nx] : CT(0);
+    P.dN = P.hasN ? dinv[k + nx] : CT(0);
+    P.dX = kx >= 0 ? dinv[kx] : CT(0);
+  }
   if (A.kind == OPK_VAR) {
     const int64_t ex = (int64_t)j * (nx + 1) + i;
     P.wt[0] = A.wx[ex];
@@ -870,28 +891,36 @@ __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t
 // updated residual rho_{i+1} is computed once, by its owner, and read by its
 // west and east neighbours from LDS; the formulas and their order are those
 // of the generic path, so the results are bitwise equal to it.
-template <typename CT>
+template <typename CT, bool PRE>
 __device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCore &d, int lpar,
                                                    int64_t k, bool own, const CGOperands<CT> &P,
                                                    CT &gam, CT &del) {
-  __shared__ CT s_r1[kBlock];
+  __shared__ CT s_z1[kBlock];
   const bool first = d.first != 0;
+  const bool pre = PRE && S->dinv != nullptr;
   const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
-  // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i
+  // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i;
+  // z = D^-1 rho with the Jacobi preconditioner, else rho; u = A z
   auto rnew = [&](CT r, CT u, CT sv) { return fmaT<CT>(-al, first ? u : fmaT<CT>(be, sv, u), r); };
+  auto znew = [&](CT r, CT u, CT sv, CT dv) {
+    const CT rn = rnew(r, u, sv);
+    return pre ? rn * dv : rn;
+  };
   const CT sk = first ? P.u : fmaT<CT>(be, P.s, P.u);
   const CT r1 = fmaT<CT>(-al, sk, P.r);
-  s_r1[threadIdx.x] = own ? r1 : CT(0);
+  const CT z1 = pre ? r1 * P.dk : r1;
+  s_z1[threadIdx.x] = own ? z1 : CT(0);
   __syncthreads();
   const int t = (int)threadIdx.x;
   CT v[4];
-  v[0] = !P.hasW ? CT(0) : (t > 0 ? s_r1[t - 1] : rnew(P.rX, P.uX, P.sX));
-  v[1] = !P.hasE ? CT(0) : (t < kBlock - 1 ? s_r1[t + 1] : rnew(P.rX, P.uX, P.sX));
-  v[2] = P.hasS ? rnew(P.rS, P.uS, P.sS) : CT(0);
-  v[3] = P.hasN ? rnew(P.rN, P.uN, P.sN) : CT(0);
-  __syncthreads();  // s_r1 is rewritten by the next tile
+  v[0] = !P.hasW ? CT(0) : (t > 0 ? s_z1[t - 1] : znew(P.rX, P.uX, P.sX, P.dX));
+  v[1] = !P.hasE ? CT(0) : (t < kBlock - 1 ? s_z1[t + 1] : znew(P.rX, P.uX, P.sX, P.dX));
+  v[2] = P.hasS ? znew(P.rS, P.uS, P.sS, P.dS) : CT(0);
+  v[3] = P.hasN ? znew(P.rN, P.uN, P.sN, P.dN) : CT(0);
+  __syncthreads();  // s_z1 is rewritten by the next tile
   if (!own || !P.m) return;
-  const CT pk = first ? P.r : fmaT<CT>(be, P.p, P.r);
+  const CT zk = pre ? P.r * P.dk : P.r;
+  const CT pk = first ? zk : fmaT<CT>(be, P.p, zk);
   ((CT *)S->wv)[k] = fmaT<CT>(al, pk, P.w);
   ((CT *)S->pv)[k] = pk;
   ((CT *)S->sq[lpar ^ 1])[k] = sk;
@@ -899,20 +928,20 @@ __device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCo
   CT u1;
   if (S->op_kind == OPK_CONST) {
     const OpView<CT> A = op_view<CT>(S);
-    u1 = A.w * ((r1 - v[0]) + (r1 - v[1]) + ((r1 - v[2]) + (r1 - v[3])));
+    u1 = A.w * ((z1 - v[0]) + (z1 - v[1]) + ((z1 - v[2]) + (z1 - v[3])));
   } else {
-    u1 = (P.wt[0] * (r1 - v[0]) + P.wt[1] * (r1 - v[1])) +
-         (P.wt[2] * (r1 - v[2]) + P.wt[3] * (r1 - v[3]));
+    u1 = (P.wt[0] * (z1 - v[0]) + P.wt[1] * (z1 - v[1])) +
+         (P.wt[2] * (z1 - v[2]) + P.wt[3] * (z1 - v[3]));
   }
   ((CT *)S->uq[lpar ^ 1])[k] = u1;
-  gam = fmaT<CT>(r1, r1, gam);
-  del = fmaT<CT>(r1, u1, del);
+  gam = fmaT<CT>(r1, z1, gam);
+  del = fmaT<CT>(z1, u1, del);
 }
 
 // Stepped form: one launch = one pass of every QP of the launch; one
 // workgroup = one tile.  Every workgroup first folds the previous launch's
 // partial sums into its own copy of the state.
-template <typename CT, bool SPEC>
+template <typename CT, bool SPEC, bool PRE>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ QPStatic ss;
@@ -929,7 +958,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
   const bool own = SPEC && kk < q->st.n;
   CGOperands<CT> P{};
-  if (own) cg_prefetch<CT>(&q->st, par, kk, P);
+  if (own) cg_prefetch<CT, PRE>(&q->st, par, kk, P);
   copy_dyn(&q->dyn[par], &sd);
   copy_static(&q->st, &ss);
   __syncthreads();
@@ -958,7 +987,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
     if (SPEC && phase == PH_CG_ITER) {
       CT gam = CT(0), del = CT(0);
-      cg_iter_prefetched<CT>(S, sd.c, par, kk, own, P, gam, del);
+      cg_iter_prefetched<CT, PRE>(S, sd.c, par, kk, own, P, gam, del);
       if (sizeof(CT) == 4) {
         accf[0] = (float)gam;
         accf[1] = (float)del;
@@ -967,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
         acc[1] = (double)del;
       }
     } else {
-      run_pass<CT>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT, PRE>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
     }
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     __syncthreads();
@@ -1032,7 +1061,7 @@ static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 // the tile, neighbours exchanged through LDS); with SPEC its loads for the
 // first tile are issued before the state is read, which costs registers in
 // every phase.
-template <typename CT, bool SPEC>
+template <typename CT, bool SPEC, bool PRE>
 __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
   __shared__ QPStatic ss;
@@ -1053,7 +1082,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
   bool own = kk < q->st.n;
   CGOperands<CT> P{};
-  if (SPEC && own) cg_prefetch<CT>(&q->st, par, kk, P);
+  if (SPEC && own) cg_prefetch<CT, PRE>(&q->st, par, kk, P);
   if (threadIdx.x < kCoreWords)
     reinterpret_cast<uint32_t *>(&sc)[threadIdx.x] =
         reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c)[threadIdx.x];
@@ -1071,10 +1100,10 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
       if (!SPEC || tile != t0) {
         kk = (int64_t)tile * kBlock + threadIdx.x;
         own = kk < S->n;
-        if (own) cg_prefetch<CT>(S, par, kk, P);
+        if (own) cg_prefetch<CT, PRE>(S, par, kk, P);
       }
       CT gam = CT(0), del = CT(0);
-      cg_iter_prefetched<CT>(S, sc, par, kk, own, P, gam, del);
+      cg_iter_prefetched<CT, PRE>(S, sc, par, kk, own, P, gam, del);
       double acc[kNP];
       float accf[2] = {(float)gam, (float)del};
 #pragma unroll
@@ -1095,7 +1124,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     float accf[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-    run_pass<CT>(S, slots, sc, phase, par, k0, k1, acc, accf);
+    run_pass<CT, PRE>(S, slots, sc, phase, par, k0, k1, acc, accf);
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
   }
@@ -1109,7 +1138,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
 // order of every sum are those of the stepped form, so results are bitwise
 // identical to it.  Every wait is bounded: after spin_limit polls the QP is
 // failed with GPCG_ERR_HANG and the workgroup exits, so the grid drains.
-template <typename CT>
+template <typename CT, bool PRE>
 __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
   __shared__ QPDyn sd;
   __shared__ int s_exit;
@@ -1147,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
       float accf[2] = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-      run_pass<CT>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT, PRE>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
       write_partial(slots, par ^ 1, phase, f32_slots(S->mixed, phase), tile, acc, accf);
       __syncthreads();
     }
@@ -1278,7 +1307,9 @@ __global__ __launch_bounds__(kBlock) void spmv_stencil_kernel(const QPDev *q,
 #pragma unroll
   for (int e = 0; e < V; ++e)
     if (((mbits >> (8 * e)) & 0xFF) == 0) out[e] = T(0);
-  *reinterpret_cast<VT *>(y + k) = *reinterpret_cast<const VT *>(out);
+  // y is written once and not read by this kernel: streaming stores
+#pragma unroll
+  for (int e = 0; e < V; ++e) __builtin_nontemporal_store(out[e], y + k + e);
 }
 
 __global__ __launch_bounds__(kBlock) void pgrad_kernel(int64_t n, const double *__restrict__ x,
@@ -1326,15 +1357,26 @@ __global__ __launch_bounds__(kBlock) void convert_f32_kernel(const double *__res
 // ------------------------------------------------------------ host launchers
 using namespace gpcg;
 
-void *gpcg_step_kernel_ptr(int mixed, int spec) {
-  if (spec) return mixed ? (void *)&step_kernel<float, true> : (void *)&step_kernel<double, true>;
-  return mixed ? (void *)&step_kernel<float, false> : (void *)&step_kernel<double, false>;
+// variant: kVarSpec | kVarPre bits
+void *gpcg_step_kernel_ptr(int mixed, int variant) {
+  const bool sp = variant & kVarSpec, pr = variant & kVarPre;
+  if (mixed) {
+    if (sp) return pr ? (void *)&step_kernel<float, true, true> : (void *)&step_kernel<float, true, false>;
+    return pr ? (void *)&step_kernel<float, false, true> : (void *)&step_kernel<float, false, false>;
+  }
+  if (sp) return pr ? (void *)&step_kernel<double, true, true> : (void *)&step_kernel<double, true, false>;
+  return pr ? (void *)&step_kernel<double, false, true> : (void *)&step_kernel<double, false, false>;
+}
+
+static const void *persistent_ptr(int mixed, int pre) {
+  if (mixed) return pre ? (const void *)&persistent_kernel<float, true> : (const void *)&persistent_kernel<float, false>;
+  return pre ? (const void *)&persistent_kernel<double, true> : (const void *)&persistent_kernel<double, false>;
 }
 
 int gpcg_persistent_max_blocks(int mixed, int *blocks_per_cu) {
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks_per_cu,
-      mixed ? (const void *)&persistent_kernel<float> : (const void *)&persistent_kernel<double>,
+      persistent_ptr(mixed, 1),
       kBlock, 0);
   return e == hipSuccess ? 0 : -1;
 }
@@ -1343,16 +1385,21 @@ int gpcg_launch_persistent(const PersistLaunch &P, int grid, int mixed, void *st
   PersistLaunch arg = P;
   void *args[] = {&arg};
   hipError_t e = hipLaunchCooperativeKernel(
-      mixed ? (const void *)&persistent_kernel<float> : (const void *)&persistent_kernel<double>,
+      persistent_ptr(mixed, P.pre),
       dim3(grid), dim3(kBlock), args, 0, (hipStream_t)stream);
   return e == hipSuccess ? 0 : -1;
 }
 
 void *gpcg_transition_kernel_ptr() { return (void *)&transition_kernel; }
 
-void *gpcg_pass_kernel_ptr(int mixed, int spec) {
-  if (spec) return mixed ? (void *)&pass_kernel<float, true> : (void *)&pass_kernel<double, true>;
-  return mixed ? (void *)&pass_kernel<float, false> : (void *)&pass_kernel<double, false>;
+void *gpcg_pass_kernel_ptr(int mixed, int variant) {
+  const bool sp = variant & kVarSpec, pr = variant & kVarPre;
+  if (mixed) {
+    if (sp) return pr ? (void *)&pass_kernel<float, true, true> : (void *)&pass_kernel<float, true, false>;
+    return pr ? (void *)&pass_kernel<float, false, true> : (void *)&pass_kernel<float, false, false>;
+  }
+  if (sp) return pr ? (void *)&pass_kernel<double, true, true> : (void *)&pass_kernel<double, true, false>;
+  return pr ? (void *)&pass_kernel<double, false, true> : (void *)&pass_kernel<double, false, false>;
 }
 
 int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
@@ -1415,6 +1462,42 @@ int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double 
                      g, pg, part);
   hipLaunchKernelGGL(pgrad_final_kernel, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
                      part, out4);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// 1 / diag(A): stencils from their weights (the same sums as the diagonal of
+// the assembled matrix), CSR from the stored diagonal entries of each row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void diag_inv_kernel(const QPDev *q, T *__restrict__ dinv) {
+  const QPStatic *S = &q->st;
+  const int64_t n = S->n;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kBlock) {
+    double dg = 0.0;
+    if (S->op_kind == OPK_CSR) {
+      for (int32_t e = S->rowptr[k]; e < S->rowptr[k + 1]; ++e)
+        if (S->colind[e] == (int32_t)k) dg += S->vals[e];
+    } else if (S->op_kind == OPK_CONST) {
+      dg = 4.0 * S->w;
+    } else {
+      const int32_t nx = S->nx;
+      const int32_t j = (int32_t)(((uint64_t)k * S->div_magic) >> S->div_shift);
+      const int32_t i = (int32_t)(k - (int64_t)j * nx);
+      const int64_t ex = (int64_t)j * (nx + 1) + i;
+      dg = (S->wx[ex] + S->wx[ex + 1]) + (S->wy[k] + S->wy[k + nx]);
+    }
+    dinv[k] = (T)(1.0 / dg);
+  }
+}
+
+int gpcg_launch_diag_inv(const QPDev *dqp, void *dinv, int f32, void *stream) {
+  const int grid = 1024;
+  if (f32)
+    hipLaunchKernelGGL(diag_inv_kernel<float>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       dqp, (float *)dinv);
+  else
+    hipLaunchKernelGGL(diag_inv_kernel<double>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       dqp, (double *)dinv);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -105,6 +105,8 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "tiles_per_wg must be in [0, 64]");
   if (o->prefetch < GPCG_PREFETCH_AUTO || o->prefetch > GPCG_PREFETCH_OFF)
     return fail(GPCG_ERR_ARG, "unknown prefetch mode");
+  if (o->precond != GPCG_PRECOND_NONE && o->precond != GPCG_PRECOND_JACOBI)
+    return fail(GPCG_ERR_ARG, "unknown preconditioner");
   return GPCG_OK;
 }
 
@@ -119,13 +121,14 @@ constexpr int kFusedMaxTiles = 1024;
 
 struct Layout {
   size_t qp, slots, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
-  size_t wx32, wy32, vals32, list, total;
+  size_t wx32, wy32, vals32, list, dinv, total;
   int tile, ntiles;
 };
 
 static_assert(kQPDevBytes % 256 == 0, "the slots follow the state at an aligned offset");
 
-Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free_set) {
+Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free_set,
+                  int precond) {
   Layout L{};
   const int64_t n = op_n(op);
   const bool mixed = precision == GPCG_PREC_MIXED;
@@ -160,6 +163,11 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free
   }
   if (mixed && op->kind == GPCG_OP_CSR) L.vals32 = take(4 * (size_t)op->nnz);
   L.list = free_set == GPCG_FREESET_LIST ? take(4 * (size_t)n) : 0;
+  // the constant stencil has a constant diagonal: Jacobi scaling leaves the
+  // CG iterates unchanged there, so it is not applied
+  L.dinv = precond == GPCG_PRECOND_JACOBI && op->kind != GPCG_OP_STENCIL5_CONST
+               ? take(ct * (size_t)n)
+               : 0;
   L.total = off;
   return L;
 }
@@ -244,6 +252,10 @@ double solve_bytes(const QPStatic &s, const QPDyn &dy) {
   B += dy.pass_count[PH_GP_ALPHA] * n * (32.0 + coef64);  // x, l, u, g
   B += dy.pass_count[PH_GP_TRIAL] * n * (56.0 + coef64);  // x, l, u, g, b in; x', g' out
   B += dy.pass_count[PH_CG_INIT] * (n * 33.0 + mean_m * (3 * c + coefc) + (n - mean_m) * 7 * c);
+  if (s.dinv) {  // the preconditioner is read once per free row and pass
+    B += (double)d.cg_free_rows * c;
+    B += dy.pass_count[PH_CG_INIT] * mean_m * c;
+  }
   if (s.list) {
     // list form: the index of each free row instead of the mask of every row;
     // the list pass reads the mask and writes the list
@@ -413,11 +425,11 @@ namespace {
 // Tuned configurations by operator shape and precision, shared by the handles
 // of the process (handles created with automatic options start from them).
 struct TuneKey {
-  int kind, nx, ny, mixed, list;
+  int kind, nx, ny, mixed, list, precond;
   int64_t n, nnz;
   bool operator<(const TuneKey &o) const {
-    return std::tie(kind, nx, ny, mixed, list, n, nnz) <
-           std::tie(o.kind, o.nx, o.ny, o.mixed, o.list, o.n, o.nnz);
+    return std::tie(kind, nx, ny, mixed, list, precond, n, nnz) <
+           std::tie(o.kind, o.nx, o.ny, o.mixed, o.list, o.precond, o.n, o.nnz);
   }
 };
 std::mutex g_tune_mu;
@@ -446,8 +458,8 @@ struct gpcg_handle_s {
 namespace {
 
 TuneKey tune_key(const gpcg_handle_s *h) {
-  return TuneKey{h->op.kind, h->st.nx, h->st.ny, h->st.mixed, h->st.list ? 1 : 0, h->st.n,
-                 h->op.kind == GPCG_OP_CSR ? h->op.nnz : 0};
+  return TuneKey{h->op.kind, h->st.nx, h->st.ny, h->st.mixed, h->st.list ? 1 : 0,
+                 h->st.dinv ? 1 : 0, h->st.n, h->op.kind == GPCG_OP_CSR ? h->op.nnz : 0};
 }
 
 void fill_static(gpcg_handle_s *h) {
@@ -490,6 +502,7 @@ void fill_static(gpcg_handle_s *h) {
   q.wv = ws + L.w;
   q.mask = (uint8_t *)(ws + L.mask);
   q.list = L.list ? (int32_t *)(ws + L.list) : nullptr;
+  q.dinv = L.dinv ? (const void *)(ws + L.dinv) : nullptr;
   q.host_flag = h->flag.dev;
   put_options(q, h->opt);
 }
@@ -553,6 +566,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->form = GPCG_FORM_AUTO;
   o->tiles_per_wg = 0;
   o->prefetch = GPCG_PREFETCH_AUTO;
+  o->precond = GPCG_PRECOND_NONE;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {
@@ -564,7 +578,7 @@ int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
-  *bytes = layout_for(op, o.precision, o.tile, o.free_set).total;
+  *bytes = layout_for(op, o.precision, o.tile, o.free_set, o.precond).total;
   return GPCG_OK;
 }
 
@@ -579,7 +593,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
-  Layout L = layout_for(op, o.precision, o.tile, o.free_set);
+  Layout L = layout_for(op, o.precision, o.tile, o.free_set, o.precond);
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
     return fail(GPCG_ERR_WORKSPACE, "workspace missing or not 256-byte aligned");
   if (ws_bytes < L.total)
@@ -633,9 +647,13 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   // building-block kernels read it; solves rewrite only the vector pointers)
   h->stage->st = h->st;
   if (hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
-                     h->stream) != hipSuccess ||
-      hipStreamSynchronize(h->stream) != hipSuccess)
+                     h->stream) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "state upload failed in create"));
+  // Jacobi preconditioner: 1 / diag(A) from the operator in the device state
+  if (L.dinv && gpcg_launch_diag_inv(h->dqp, h->ws + L.dinv, h->st.mixed, h->stream) != 0)
+    return cleanup(fail(GPCG_ERR_HIP, "preconditioner set-up failed"));
+  if (hipStreamSynchronize(h->stream) != hipSuccess)
+    return cleanup(fail(GPCG_ERR_HIP, "stream synchronize failed in create"));
   *out = h;
   return GPCG_OK;
 }
@@ -665,19 +683,20 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   SL.nqp = 1;
   SL.total_tiles = h->L.ntiles;
   const LaunchCfg c = h->cfg;
+  const int variant = (c.spec ? kVarSpec : 0) | (h->st.dinv ? kVarPre : 0);
   SL.tiles_per_wg = c.tiles_per_wg;
   SL.data_grid = (h->L.ntiles + c.tiles_per_wg - 1) / c.tiles_per_wg;
   const int chunk = c.chunk;
   if (h->opt.use_graph && (!h->graph || h->graph_cfg != c)) {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
-    rc = build_chain_graph(SL, h->st.mixed, c.spec, c.split, chunk, &h->graph);
+    rc = build_chain_graph(SL, h->st.mixed, variant, c.split, chunk, &h->graph);
     if (rc) return rc;
     h->graph_cfg = c;
   }
   int64_t launches = 0, checks = 0;
   volatile int32_t *flag = h->flag.host;
-  rc = run_until(h->stream, SL, h->st.mixed, c.spec, c.split, chunk,
+  rc = run_until(h->stream, SL, h->st.mixed, variant, c.split, chunk,
                  h->opt.use_graph ? h->graph : nullptr, h->ev,
                  [&] { return *flag != 0; }, (int64_t)1 << 26, &launches, &checks);
   if (rc) return rc;
@@ -1065,7 +1084,9 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     }
     const int grid = pre[cnt];
     HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
-    PersistLaunch P{b->qptrs, b->prefix, cnt, grid, (int64_t)1 << 22};
+    int pre = 0;
+    for (int i = 0; i < cnt; ++i) pre |= b->hs[i]->st.dinv ? 1 : 0;
+    PersistLaunch P{b->qptrs, b->prefix, cnt, grid, (int64_t)1 << 22, pre, 0};
     if (gpcg_launch_persistent(P, grid, b->mixed, b->stream) != 0)
       return fail(GPCG_ERR_HIP, std::string("cooperative launch failed: ") +
                                     hipGetErrorString(hipGetLastError()));
@@ -1098,8 +1119,12 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       SL.total_tiles = total;
       SL.tiles_per_wg = T;
       SL.data_grid = nitems;
-      bool spec = b->cfg.spec != 0;
-      for (int i : active) spec = spec && spec_ok(b->hs[i]->st);
+      bool sp = b->cfg.spec != 0, pre = false;
+      for (int i : active) {
+        sp = sp && spec_ok(b->hs[i]->st);
+        pre = pre || b->hs[i]->st.dinv != nullptr;
+      }
+      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0);
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
       if (rc) return rc;
@@ -1237,7 +1262,7 @@ struct ReqLayout {
 
 ReqLayout req_layout(const gpcg_operator *op, int precision) {
   ReqLayout R{};
-  R.L = layout_for(op, precision, 0, GPCG_FREESET_MASK);
+  R.L = layout_for(op, precision, 0, GPCG_FREESET_MASK, GPCG_PRECOND_NONE);
   const int64_t n = op_n(op);
   size_t off = R.L.total;
   auto take = [&](size_t bytes) {

@@ -183,6 +183,129 @@ def pin_reduced_cg_stays_on_face(o):
     assert np.allclose(d[F], np.linalg.solve(A[np.ix_(F, F)], -g[F]), rtol=1e-9, atol=1e-12)
 
 
+def _textbook_pcg(A, rhs, dinv, iters):
+    """Preconditioned CG for A w = rhs from w = 0 with M^{-1} = diag(dinv),
+    written from the textbook; returns the iterates."""
+    w = np.zeros_like(rhs)
+    r = rhs.copy()
+    z = dinv * r
+    p = z.copy()
+    out = []
+    for _ in range(iters):
+        Ap = A @ p
+        a = (r @ z) / (p @ Ap)
+        w = w + a * p
+        r_new = r - a * Ap
+        z_new = dinv * r_new
+        out.append(w.copy())
+        if r_new @ z_new == 0:
+            break
+        p = z_new + (r_new @ z_new) / (r @ z) * p
+        r, z = r_new, z_new
+    return out
+
+
+def pin_reduced_pcg_is_textbook_pcg(o):
+    """Diagonal preconditioner on a badly scaled SPD matrix: the iterates are
+    textbook preconditioned CG with M = diag(A_k), the decreases equal
+    q_k(w_{j-1}) - q_k(w_j), and on a free subset the preconditioner is the
+    diagonal of the reduced matrix (eq. (cg2))."""
+    rng = np.random.default_rng(21)
+    Q = rng.standard_normal((8, 8))
+    S = np.diag(10.0 ** rng.uniform(-2, 2, 8))
+    A = S @ (Q.T @ Q + 0.5 * np.eye(8)) @ S  # SPD, diagonal spread over 1e8
+    csr = instances.dense_to_csr(A)
+    g = rng.standard_normal(8)
+    mask = np.ones(8, np.uint8)
+    ref = _textbook_pcg(A, -g, 1.0 / np.diag(A), 8)
+    for k in (1, 2, 3):
+        st, d, it, _ = o.reduced_cg(csr, mask, g, 1e-300, max_cg=k, precond=1)
+        assert st == 0 and it == k
+        assert np.allclose(d, ref[k - 1], rtol=1e-9, atol=1e-12 * np.abs(ref[k - 1]).max())
+    st, d, it, decs = o.reduced_cg(csr, mask, g, 1e-300, precond=1)
+    assert st == 0 and 1 <= it <= 8
+    assert np.allclose(d, np.linalg.solve(A, -g), rtol=1e-7)
+    qk = lambda w: 0.5 * w @ A @ w + g @ w
+    prev = 0.0
+    for j in range(min(it, 3)):
+        cur = qk(ref[j])
+        assert np.isclose(decs[j], prev - cur, rtol=1e-7), (j, decs[j], prev - cur)
+        prev = cur
+    # the unpreconditioned iterates differ on this matrix: the option is live
+    st0, d0, _, _ = o.reduced_cg(csr, mask, g, 1e-300, max_cg=2)
+    assert not np.allclose(d0, ref[1], rtol=1e-6)
+    # a free subset: the preconditioner is the diagonal of A_FF
+    F = np.array([1, 1, 0, 1, 0, 1, 1, 0], bool)
+    refF = _textbook_pcg(A[np.ix_(F, F)], -g[F], 1.0 / np.diag(A)[F], 5)
+    st, d, it, _ = o.reduced_cg(csr, F.astype(np.uint8), g, 1e-300, max_cg=2, precond=1)
+    assert st == 0 and np.all(d[~F] == 0.0)
+    assert np.allclose(d[F], refF[1], rtol=1e-9, atol=1e-12 * np.abs(refF[1]).max())
+
+
+def pin_pcg_decrease_identity_exact(o):
+    """For preconditioned CG, 1/2 alpha_j rho_j'z_j = q_k(w_{j-1}) - q_k(w_j)
+    holds exactly: the recurrence run in rational arithmetic on a small SPD
+    system, and the oracle's floating-point decreases agree with it."""
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(5)
+    n = 5
+    Q = rng.integers(-3, 4, (n, n))
+    Ai = Q.T @ Q + np.diag(rng.integers(1, 9, n))
+    gi = rng.integers(-5, 6, n)
+    A = [[Fr(int(v)) for v in row] for row in Ai]
+    g = [Fr(int(v)) for v in gi]
+    dinv = [1 / A[i][i] for i in range(n)]
+    mv = lambda v: [sum(A[i][k] * v[k] for k in range(n)) for i in range(n)]
+    dot = lambda a, b: sum(x * y for x, y in zip(a, b))
+    qk = lambda w: Fr(1, 2) * dot(w, mv(w)) + dot(g, w)
+    w = [Fr(0)] * n
+    r = [-v for v in g]
+    z = [di * ri for di, ri in zip(dinv, r)]
+    p = list(z)
+    exact_decs = []
+    for _ in range(n):
+        Ap = mv(p)
+        rz = dot(r, z)
+        a = rz / dot(p, Ap)
+        w_new = [wi + a * pi for wi, pi in zip(w, p)]
+        dec = Fr(1, 2) * a * rz
+        assert dec == qk(w) - qk(w_new)
+        exact_decs.append(dec)
+        r = [ri - a * api for ri, api in zip(r, Ap)]
+        z = [di * ri for di, ri in zip(dinv, r)]
+        w = w_new
+        if dot(r, z) == 0:
+            break
+        p = [zi + dot(r, z) / rz * pi for zi, pi in zip(z, p)]
+    csr = instances.dense_to_csr(Ai.astype(float))
+    st, d, it, decs = o.reduced_cg(csr, np.ones(n, np.uint8), gi.astype(float), 1e-300,
+                                   max_cg=len(exact_decs), precond=1)
+    assert st == 0
+    for j in range(it):
+        assert abs(decs[j] - float(exact_decs[j])) <= 1e-11 * abs(float(exact_decs[j])), j
+
+
+def pin_jacobi_gpcg_same_solution(o):
+    """GPCG with the diagonal preconditioner reaches the same x* as without it
+    (x* does not depend on the preconditioner), on the obstacle problem and on
+    a strongly varying coefficient, where it needs far fewer CG iterations."""
+    inst = instances.obstacle50(0)
+    xs, info = exact.polish(inst.csr(), inst.b, inst.l, inst.u, None)
+    assert info["converged"]
+    x1, _, st1 = o.solve_instance(inst, precond=1, **TIGHT)
+    assert st1["status"] == 0
+    assert np.abs(x1 - xs).max() <= 1e-9 * max(1.0, np.abs(xs).max())
+    vc = instances.varcoef(40, 2, eps=0.9)
+    vc.l = np.full(vc.n, -np.inf)  # unconstrained: x* = A^{-1} b
+    vc.u = np.full(vc.n, np.inf)
+    want = np.linalg.solve(exact.csr_matrix(vc.csr()).toarray(), vc.b)
+    x0, _, s0 = o.solve_instance(vc, **TIGHT)
+    xj, _, sj = o.solve_instance(vc, precond=1, **TIGHT)
+    for x in (x0, xj):
+        assert np.abs(x - want).max() <= 1e-9 * np.abs(want).max()
+    assert sj["cg_iters"] < 0.5 * s0["cg_iters"], (sj["cg_iters"], s0["cg_iters"])
+
+
 # ---------------------------------------------------------------- whole method
 
 def pin_brute_force_tiny(o, count=40):
@@ -288,6 +411,8 @@ ALL_PINS = [
     pin_decrease_identity_exact,
     pin_reduced_cg_is_textbook_cg,
     pin_reduced_cg_stays_on_face,
+    pin_reduced_pcg_is_textbook_pcg,
+    pin_pcg_decrease_identity_exact,
     pin_brute_force_tiny,
     pin_diagonal_closed_form,
     pin_unconstrained_laplacian_dst,
@@ -295,4 +420,5 @@ ALL_PINS = [
     pin_manufactured,
     pin_matches_independent_exact_solver,
     pin_invariants,
+    pin_jacobi_gpcg_same_solution,
 ]
