@@ -163,7 +163,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(inst, budget_s=12.0, precond=0):
+def cpu_baseline(inst, budget_s=12.0, precond=0, cg_stop=0):
     """The FP64 oracle, as it stands, on this host: solves/sec on a bounded
     sample (whole solves of the same workload until the budget is spent)."""
     import oracle
@@ -172,7 +172,7 @@ def cpu_baseline(inst, budget_s=12.0, precond=0):
     t0 = time.perf_counter()
     k = 0
     while True:
-        ora.gpcg(csr, inst.b, inst.l, inst.u, inst.x0, precond=precond)
+        ora.gpcg(csr, inst.b, inst.l, inst.u, inst.x0, precond=precond, cg_stop=cg_stop)
         k += 1
         el = time.perf_counter() - t0
         if el >= budget_s or k >= 200:
@@ -416,6 +416,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="passes per graph replay (0 = default)")
     ap.add_argument("--precond", default="none", choices=["none", "jacobi"],
                     help="preconditioner of the reduced CG")
+    ap.add_argument("--cg-stop", default="decrease", choices=["decrease", "residual"],
+                    help="CG stopping test: relative decrease (the paper's) or residual")
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
                     help="free set of the reduced CG: byte mask or compacted list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -472,8 +474,9 @@ def main():
     pf = {"auto": gpcg.GPCG_PREFETCH_AUTO, "on": gpcg.GPCG_PREFETCH_ON,
           "off": gpcg.GPCG_PREFETCH_OFF}[args.prefetch]
     pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
+    cs = gpcg.GPCG_CGSTOP_RESIDUAL if args.cg_stop == "residual" else gpcg.GPCG_CGSTOP_DECREASE
     solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf, precond=pc,
-                         tiles_per_wg=args.tiles_per_wg, chunk=args.chunk, **opts)
+                         cg_stop=cs, tiles_per_wg=args.tiles_per_wg, chunk=args.chunk, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
 
@@ -545,7 +548,7 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n": inst.n,
                    "free_set": args.free_set, "form": args.form,
                    "tiles_per_wg": args.tiles_per_wg, "prefetch": args.prefetch,
-                   "precond": args.precond,
+                   "precond": args.precond, "cg_stop": args.cg_stop,
                    "chunk": args.chunk,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
@@ -571,7 +574,8 @@ def main():
         res["extras"] = spmv_extras(gpcg, torch, dev)
     solver.close()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inst, precond=int(args.precond == "jacobi"))
+        res["cpu_baseline"] = cpu_baseline(inst, precond=int(args.precond == "jacobi"),
+                                           cg_stop=int(args.cg_stop == "residual"))
     print(json.dumps(res), flush=True)
 
 

@@ -129,10 +129,15 @@ typedef struct {
                           the CG iterates and counts are not.  The constant
                           stencil has a constant diagonal, which leaves the
                           iterates unchanged: there it is not applied      */
+  int32_t cg_stop;      /* GPCG_CGSTOP_DECREASE (default) or _RESIDUAL       */
 } gpcg_options;
 
 #define GPCG_PRECOND_NONE 0
 #define GPCG_PRECOND_JACOBI 1
+#define GPCG_CGSTOP_DECREASE 0 /* eq. (cgstop1): relative decrease of q_k         */
+#define GPCG_CGSTOP_RESIDUAL 1 /* ||r_k + A_k w_j|| <= eta_2 ||r_k||, the standard
+                                  test the paper contrasts with eq. (cgstop1)
+                                  (M^-1 norm when preconditioned)               */
 
 #define GPCG_PREFETCH_AUTO 0
 #define GPCG_PREFETCH_ON 1
@@ -148,7 +153,7 @@ typedef struct {
  * eta2_reduce 0.1, mu 0.01, max_outer 100000, max_gp 50, max_backtrack 60,
  * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
  * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO,
- * precond GPCG_PRECOND_NONE. */
+ * precond GPCG_PRECOND_NONE, cg_stop GPCG_CGSTOP_DECREASE. */
 void gpcg_options_default(gpcg_options *opt);
 
 /* ------------------------------------------------------------------- stats */

@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("eta2", C.c_double), ("eta2_reduce", C.c_double), ("mu", C.c_double),
                 ("max_outer", C.c_int32), ("max_gp", C.c_int32),
                 ("max_backtrack", C.c_int32), ("max_cg", C.c_int32), ("max_stall", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("cg_stop", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -109,7 +109,8 @@ class Oracle:
         L.ora_classify.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         L.ora_gp_alpha0.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ora_trial.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp, vp, vp]
-        L.ora_reduced_cg.argtypes = [vp, vp, vp, d, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32]
+        L.ora_reduced_cg.argtypes = [vp, vp, vp, d, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp,
+                                     C.c_int32]
         L.ora_reduced_cg.restype = C.c_int
         L.ora_decrease.argtypes = [d, d]
         L.ora_decrease.restype = d
@@ -195,7 +196,7 @@ class Oracle:
     def decrease(self, gs, sAs):
         return self.lib.ora_decrease(float(gs), float(sAs))
 
-    def reduced_cg(self, csr, free_mask, g, eta, max_cg=0, dec_cap=4096, precond=0):
+    def reduced_cg(self, csr, free_mask, g, eta, max_cg=0, dec_cap=4096, precond=0, cg_stop=0):
         A, keep = self._csr(csr)
         fm = np.ascontiguousarray(free_mask, dtype=np.uint8)
         g = _f64(g)
@@ -203,7 +204,8 @@ class Oracle:
         it = C.c_int32()
         decs = np.zeros(dec_cap)
         st = self.lib.ora_reduced_cg(C.byref(A), _ptr(fm), _ptr(g), float(eta), int(max_cg),
-                                     int(precond), _ptr(d), C.byref(it), _ptr(decs), dec_cap)
+                                     int(precond), int(cg_stop), _ptr(d), C.byref(it),
+                                     _ptr(decs), dec_cap)
         return st, d, it.value, decs[:min(it.value, dec_cap)]
 
     # -- the whole method

@@ -47,7 +47,10 @@
  *    q_k(w_{j-1})-q_k(w_j));
  *  - the reduced CG may be preconditioned by the diagonal of A_k (the point
  *    Jacobi preconditioner of the paper's Section "Preconditioners"); the
- *    default is no preconditioner.
+ *    default is no preconditioner;
+ *  - the CG may instead stop by the residual test that the paper contrasts
+ *    with eq. (cgstop1), ||r_k + A_k w_j|| <= eta_2 ||r_k||, measured in the
+ *    M^{-1} norm when preconditioned; the default is eq. (cgstop1).
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
  * round-to-nearest, sequential sums in index order).
@@ -83,6 +86,7 @@ typedef struct {
   int32_t max_outer, max_gp, max_backtrack, max_cg; /* max_cg <= 0: m_k */
   int32_t max_stall; /* outer iterations without a new best ||P grad q|| */
   int32_t precond;   /* reduced CG: 0 none, 1 diagonal (Jacobi) of A_k */
+  int32_t cg_stop;   /* reduced CG: 0 relative decrease (cgstop1), 1 residual */
 } ora_options;
 
 typedef struct {
@@ -109,6 +113,7 @@ void ora_default_options(ora_options *o) {
   o->max_cg = 0;
   o->max_stall = 25;
   o->precond = 0;
+  o->cg_stop = 0;
 }
 
 /* ----------------------------------------------------------- building blocks */
@@ -308,8 +313,8 @@ static void extract_submatrix(const ora_csr *A, const int64_t *F, int64_t m, con
  * ORA_ERR_NOT_SPD; *iters gets the number of CG iterations; decs (optional,
  * capacity dec_cap) receives q_k(w_{j-1}) - q_k(w_j) for each iteration. */
 int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const double *g,
-                   double eta, int32_t max_cg, int32_t precond, double *d, int32_t *iters,
-                   double *decs, int32_t dec_cap) {
+                   double eta, int32_t max_cg, int32_t precond, int32_t cg_stop, double *d,
+                   int32_t *iters, double *decs, int32_t dec_cap) {
   int64_t n = A->n;
   int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
@@ -364,6 +369,7 @@ int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const doubl
     p[a] = z[a];
   }
   double rz = ora_dot(m, rho, z);
+  const double rz0 = rz;
   int64_t cap = max_cg > 0 ? max_cg : m;
   double decmax = -INFINITY;
   int32_t j = 0;
@@ -389,7 +395,16 @@ int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const doubl
       double dec = 0.5 * alpha * rz;
 #endif
       if (decs && j <= dec_cap) decs[j - 1] = dec;
-      int stop = (rz_new == 0.0) || (j >= 2 && dec <= eta * decmax) || (j >= cap);
+      /* eq. (cgstop1); or the standard residual test the paper sets it
+       * against, ||r_k + A_k w_j|| <= eta ||r_k|| (in the M^{-1} norm when
+       * preconditioned: rho'z) */
+      int stop = (rz_new == 0.0) || (j >= cap);
+#if ORA_MUTANT == 12
+      if (cg_stop == 1) stop = stop || (rz_new <= eta * rz0);
+#else
+      if (cg_stop == 1) stop = stop || (sqrt(rz_new) <= eta * sqrt(rz0));
+#endif
+      else stop = stop || (j >= 2 && dec <= eta * decmax);
       if (dec > decmax) decmax = dec;
       if (stop) break;
 #if ORA_MUTANT == 5
@@ -557,7 +572,8 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
         break;
       }
       int32_t it = 0;
-      int cgs = ora_reduced_cg(A, fm, g, eta, opt.max_cg, opt.precond, d, &it, NULL, 0);
+      int cgs = ora_reduced_cg(A, fm, g, eta, opt.max_cg, opt.precond, opt.cg_stop, d, &it,
+                               NULL, 0);
       st->cg_iters += it;
       ++st->cg_phases;
       if (cgs != ORA_OK) {

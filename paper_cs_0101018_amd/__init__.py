@@ -39,6 +39,7 @@ GPCG_BATCH_STEPPED, GPCG_BATCH_PERSISTENT = 0, 1
 GPCG_FORM_AUTO, GPCG_FORM_FUSED, GPCG_FORM_SPLIT = 0, 1, 2
 GPCG_PREFETCH_AUTO, GPCG_PREFETCH_ON, GPCG_PREFETCH_OFF = 0, 1, 2
 GPCG_PRECOND_NONE, GPCG_PRECOND_JACOBI = 0, 1
+GPCG_CGSTOP_DECREASE, GPCG_CGSTOP_RESIDUAL = 0, 1
 
 
 class gpcg_operator(C.Structure):
@@ -55,7 +56,7 @@ class gpcg_options(C.Structure):
                 ("tile", C.c_int32), ("chunk", C.c_int32), ("use_graph", C.c_int32),
                 ("max_stall", C.c_int32), ("form", C.c_int32),
                 ("tiles_per_wg", C.c_int32), ("prefetch", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("cg_stop", C.c_int32)]
 
 
 class gpcg_stats(C.Structure):

@@ -43,7 +43,7 @@ enum PhaseBucket : int32_t { TB_CG = 0, TB_GP = 1, TB_SEARCH = 2, TB_OTHER = 3 }
 struct QPStatic {
   int32_t op_kind, nx, ny, tile;  // tile: unknowns per workgroup and pass
   int32_t ntiles, mixed, max_outer, max_gp;
-  int32_t max_backtrack, max_cg, max_stall, pad0;
+  int32_t max_backtrack, max_cg, max_stall, cg_stop;  // cg_stop: 0 eq. (cgstop1), 1 residual
   int64_t n;
   uint64_t div_magic;  // k / nx == (k * div_magic) >> div_shift for k < 2^30
   int32_t div_shift, pad1;
@@ -74,7 +74,7 @@ struct QPCore {
   int32_t cg_iters, backtracks, face_repeats, cg_phases;
   double tau, pg0, pgn, q, best_pg;
   double alpha, gp_decmax;
-  double eta, cg_alpha, cg_beta, gamma, cg_decmax;
+  double eta, cg_alpha, cg_beta, gamma, cg_decmax, gamma0;
   int64_t m_free, n_lower, n_upper, n_nonbinding;
   int64_t passes, cg_free_rows;
 };

@@ -705,6 +705,7 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
       d.max_cg_eff = S->max_cg > 0 ? S->max_cg : (int32_t)m;
       d.first = 1;
       d.gamma = R[0];
+      d.gamma0 = R[0];
       if (!(d.gamma > 0.0)) start_ps(d);  // r_k = 0: the CG direction is 0
       else if (!(R[1] > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
       else {
@@ -721,8 +722,11 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
       d.cg_iters += 1;
       d.cg_free_rows += d.m_free;  // unknowns this CG pass swept with full traffic
       const double dec = 0.5 * d.cg_alpha * d.gamma;  // q_k(w_{j-1}) - q_k(w_j)
-      const bool stop = (R[0] == 0.0) || (d.cg_j >= 2 && dec <= d.eta * d.cg_decmax) ||
-                        (d.cg_j >= d.max_cg_eff);  // eq. (cgstop1)
+      // eq. (cgstop1), or the residual test ||rho_j|| <= eta ||rho_0|| (M^-1 norm
+      // with the preconditioner: gamma = rho'z)
+      const bool test = S->cg_stop ? sqrt(R[0]) <= d.eta * sqrt(d.gamma0)
+                                   : (d.cg_j >= 2 && dec <= d.eta * d.cg_decmax);
+      const bool stop = (R[0] == 0.0) || test || (d.cg_j >= d.max_cg_eff);
       if (dec > d.cg_decmax) d.cg_decmax = dec;
       d.first = 0;
       if (stop) start_ps(d);

@@ -107,6 +107,8 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "unknown prefetch mode");
   if (o->precond != GPCG_PRECOND_NONE && o->precond != GPCG_PRECOND_JACOBI)
     return fail(GPCG_ERR_ARG, "unknown preconditioner");
+  if (o->cg_stop != GPCG_CGSTOP_DECREASE && o->cg_stop != GPCG_CGSTOP_RESIDUAL)
+    return fail(GPCG_ERR_ARG, "unknown CG stopping test");
   return GPCG_OK;
 }
 
@@ -216,6 +218,7 @@ void put_options(QPStatic &s, const gpcg_options &o) {
   s.max_backtrack = o.max_backtrack;
   s.max_cg = o.max_cg;
   s.max_stall = o.max_stall;
+  s.cg_stop = o.cg_stop;
 }
 
 // The initial state of a solve (phase INIT, nothing pending).
@@ -567,6 +570,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->tiles_per_wg = 0;
   o->prefetch = GPCG_PREFETCH_AUTO;
   o->precond = GPCG_PRECOND_NONE;
+  o->cg_stop = GPCG_CGSTOP_DECREASE;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {

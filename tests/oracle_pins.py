@@ -306,6 +306,36 @@ def pin_jacobi_gpcg_same_solution(o):
     assert sj["cg_iters"] < 0.5 * s0["cg_iters"], (sj["cg_iters"], s0["cg_iters"])
 
 
+def pin_residual_cg_stop(o):
+    """The residual test (cg_stop = 1): CG stops at the first iterate whose
+    residual ||r_k + A_k w_j|| is at most eta ||r_k||, found here by running
+    textbook CG; with the Jacobi preconditioner the norm is the M^{-1} norm."""
+    inst = instances.tiny_dense(8, seed=12, scale=3.0)
+    A = inst.dense
+    csr = inst.csr()
+    g = np.random.default_rng(3).standard_normal(8)
+    mask = np.ones(8, np.uint8)
+    for eta in (0.5, 0.1, 1e-3):
+        ref = _textbook_cg(A, -g, 8)
+        r0 = np.linalg.norm(g)
+        want = next(j for j, w in enumerate(ref) if np.linalg.norm(g + A @ w) <= eta * r0) + 1
+        st, d, it, _ = o.reduced_cg(csr, mask, g, eta, cg_stop=1)
+        assert st == 0 and it == want, (eta, it, want)
+        assert np.allclose(d, ref[it - 1], rtol=1e-9, atol=1e-12)
+    dinv = 1.0 / np.diag(A)
+    refp = _textbook_pcg(A, -g, dinv, 8)
+    mnorm = lambda r: np.sqrt(r @ (dinv * r))
+    want = next(j for j, w in enumerate(refp) if mnorm(-g - A @ w) <= 0.1 * mnorm(-g)) + 1
+    st, d, it, _ = o.reduced_cg(csr, mask, g, 0.1, cg_stop=1, precond=1)
+    assert st == 0 and it == want
+    # the whole method reaches the same x* with either test
+    inst = instances.obstacle50(2)
+    xs, info = exact.polish(inst.csr(), inst.b, inst.l, inst.u, None)
+    x, _, st = o.solve_instance(inst, cg_stop=1, **TIGHT)
+    assert info["converged"] and st["status"] == 0
+    assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
+
+
 # ---------------------------------------------------------------- whole method
 
 def pin_brute_force_tiny(o, count=40):
@@ -413,6 +443,7 @@ ALL_PINS = [
     pin_reduced_cg_stays_on_face,
     pin_reduced_pcg_is_textbook_pcg,
     pin_pcg_decrease_identity_exact,
+    pin_residual_cg_stop,
     pin_brute_force_tiny,
     pin_diagonal_closed_form,
     pin_unconstrained_laplacian_dst,

@@ -96,3 +96,34 @@ def test_jacobi_batch_equals_alone(mode):
     bt.close()
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("name,make,prec,pc", [
+    ("c0", lambda: instances.obstacle50(0), 0, 0),
+    ("c1", lambda: instances.varcoef256(0), 0, 0),
+    ("c1_jacobi", lambda: instances.varcoef256(0), 0, 1),
+    ("c1_mixed", lambda: instances.varcoef256(0), 1, 0),
+])
+def test_residual_cg_stop_matches_oracle(name, make, prec, pc):
+    """The residual CG test (cg_stop = GPCG_CGSTOP_RESIDUAL) against the
+    polished x*; its CG counts track the oracle's with the same test."""
+    import paper_cs_0101018_amd as gpcg
+    inst = make()
+    xs, gs, _ = reference(name.split("_")[0], inst)
+    tol, bar = (TIGHT, 1e-8) if prec == 0 else (1e-10, 1e-6)
+    x, g, st = G.solve(inst, precision=prec, tol_rel=tol, precond=pc,
+                       cg_stop=gpcg.GPCG_CGSTOP_RESIDUAL)
+    err = G.rel_inf(x, xs)
+    print(f"residual stop {name}: status={st['status']} cg={st['cg_iters']} err={err:.2e}",
+          flush=True)
+    assert st["status"] == gpcg.GPCG_OK, st
+    assert err <= bar
+    check_faces(x, xs, gs, inst)
+    if prec == 0:
+        _, _, so = oracle.default().solve_instance(inst, precond=pc, cg_stop=1)
+        _, _, sg = G.solve(inst, precond=pc, cg_stop=gpcg.GPCG_CGSTOP_RESIDUAL)
+        assert abs(sg["cg_iters"] - so["cg_iters"]) <= 0.2 * so["cg_iters"] + 5, (sg, so)
+    # the launch forms agree bitwise under this test as well
+    xa, _, _ = G.solve(inst, precision=prec, precond=pc, cg_stop=1, form=gpcg.GPCG_FORM_FUSED)
+    xb, _, _ = G.solve(inst, precision=prec, precond=pc, cg_stop=1, form=gpcg.GPCG_FORM_SPLIT)
+    assert np.array_equal(xa, xb)

@@ -14,13 +14,14 @@ swaps in one plausible mistake (CPU only; nothing here touches a GPU):
  9  binding test with the inequalities reversed
 10  CG decrease without the 1/2
 11  preconditioned CG updates the direction with rho instead of z = M^{-1} rho
+12  the residual CG test compares squared norms against eta
 """
 import pytest
 
 import oracle
 from tests import oracle_pins
 
-MUTANTS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11]
+MUTANTS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12]
 
 
 @pytest.fixture(scope="module")
