@@ -173,6 +173,21 @@ def test_fused_and_split_forms_agree_bitwise(case):
             assert st[k] == s1[k], k
 
 
+def test_wider_tiles():
+    """512-unknown tiles (two unknowns per thread and pass, no early loads):
+    the same parity bar, and the launch forms agree bitwise."""
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.obstacle(77, 3, amplitude=0.45, u_random=True)
+    xs, gs, _ = reference("obst_ragged", inst)
+    x, g, st = G.solve(inst, tol_rel=TIGHT, tile=512)
+    assert st["status"] == gpcg.GPCG_OK, st
+    assert G.rel_inf(x, xs) <= 1e-8
+    check_faces(x, xs, gs, inst)
+    xf, _, _ = G.solve(inst, tile=512, form=gpcg.GPCG_FORM_FUSED)
+    xp, _, _ = G.solve(inst, tile=512, form=gpcg.GPCG_FORM_SPLIT)
+    assert np.array_equal(xf, xp)
+
+
 def test_start_outside_box_is_projected():
     inst = instances.obstacle50(4)
     inst.x0 = inst.x0.copy()
