@@ -942,6 +942,94 @@ __device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCo
   del = fmaT<CT>(z1, u1, del);
 }
 
+// Operands of a gradient-projection pass at unknown k of a stencil QP, loaded
+// while the transition of the previous pass is still running: x, l, u, g at
+// k and its west, east, south and north neighbours (index 0..4; 0 outside the
+// grid), b at k, and the edge weights.  x and g are those of copy cp, the copy
+// the next pass is predicted to read.
+struct GPOperands {
+  double x[5], l[5], u[5], g[5];
+  double b;
+  double wt[4];
+  bool has[4];  // W, E, S, N inside the grid
+};
+
+__device__ __forceinline__ void gp_prefetch(const QPStatic *S, int cp, int64_t k, GPOperands &G) {
+  const int32_t nx = S->nx;
+  const int32_t j = (int32_t)(((uint64_t)k * S->div_magic) >> S->div_shift);
+  const int32_t i = (int32_t)(k - (int64_t)j * nx);
+  G.has[0] = i > 0;
+  G.has[1] = i < nx - 1;
+  G.has[2] = j > 0;
+  G.has[3] = j < S->ny - 1;
+  const int64_t nb[5] = {k, k - 1, k + 1, k - nx, k + nx};
+  const double *__restrict__ x = S->x[cp];
+  const double *__restrict__ g = S->g[cp];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const bool in = q == 0 || G.has[q - 1];
+    G.x[q] = in ? x[nb[q]] : 0.0;
+    G.l[q] = in ? S->l[nb[q]] : 0.0;
+    G.u[q] = in ? S->u[nb[q]] : 0.0;
+    G.g[q] = in ? g[nb[q]] : 0.0;
+  }
+  G.b = S->b[k];
+  if (S->op_kind == OPK_VAR) {
+    const int64_t ex = (int64_t)j * (nx + 1) + i;
+    G.wt[0] = S->wx[ex];
+    G.wt[1] = S->wx[ex + 1];
+    G.wt[2] = S->wy[k];
+    G.wt[3] = S->wy[k + nx];
+  }
+}
+
+// The stencil row of apply_row / apply_row2 on values at (k, W, E, S, N).
+__device__ __forceinline__ double row5(const QPStatic *S, const double *wt, const bool *has,
+                                       double c, double vW, double vE, double vS, double vN) {
+  vW = has[0] ? vW : 0.0;
+  vE = has[1] ? vE : 0.0;
+  vS = has[2] ? vS : 0.0;
+  vN = has[3] ? vN : 0.0;
+  if (S->op_kind == OPK_CONST) return S->w * ((c - vW) + (c - vE) + ((c - vS) + (c - vN)));
+  return (wt[0] * (c - vW) + wt[1] * (c - vE)) + (wt[2] * (c - vS) + wt[3] * (c - vN));
+}
+
+// GP_ALPHA and GP_TRIAL of run_pass on prefetched operands (one unknown per
+// thread, own: k is an unknown of the QP); the same formulas in the same
+// order, so the results are bitwise equal.
+__device__ __forceinline__ void gp_pass_prefetched(const QPStatic *S, const QPCore &d, int phase,
+                                                   int64_t k, bool own, const GPOperands &G,
+                                                   double (&acc)[kNP]) {
+  if (!own) return;
+  if (phase == PH_GP_ALPHA) {
+    double dv[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) dv[q] = proj_grad(G.x[q], G.l[q], G.u[q], G.g[q]);
+    const double Adk = row5(S, G.wt, G.has, dv[0], dv[1], dv[2], dv[3], dv[4]);
+    acc[0] = __fma_rn(dv[0], dv[0], acc[0]);
+    acc[1] = __fma_rn(dv[0], Adk, acc[1]);
+    return;
+  }
+  // PH_GP_TRIAL
+  const double a = d.alpha;
+  double y[5], sv[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    y[q] = gp_point(G.x[q], G.l[q], G.u[q], G.g[q], a);
+    sv[q] = y[q] - G.x[q];
+  }
+  const double Ay = row5(S, G.wt, G.has, y[0], y[1], y[2], y[3], y[4]);
+  const double As = row5(S, G.wt, G.has, sv[0], sv[1], sv[2], sv[3], sv[4]);
+  const double xk = G.x[0], lk = G.l[0], uk = G.u[0], gk = G.g[0], bk = G.b;
+  const double gy = Ay - bk;
+  S->x[d.cur ^ 1][k] = y[0];
+  S->g[d.cur ^ 1][k] = gy;
+  face_acc(y[0], lk, uk, gy, bk, acc);
+  acc[5] = __fma_rn(gk, sv[0], acc[5]);
+  acc[6] = __fma_rn(sv[0], As, acc[6]);
+  acc[7] += (is_active(y[0], lk, uk) != is_active(xk, lk, uk)) ? 1.0 : 0.0;
+}
+
 // Stepped form: one launch = one pass of every QP of the launch; one
 // workgroup = one tile.  Every workgroup first folds the previous launch's
 // partial sums into its own copy of the state.
@@ -968,6 +1056,16 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __syncthreads();
   const QPStatic *S = &ss;
   const int ntiles = S->ntiles, mixed = S->mixed;
+  // gradient-projection operands for the likely next pass, loaded while the
+  // transition runs: after GP_ALPHA comes GP_TRIAL on the same copy of x, g;
+  // after GP_TRIAL (accepted, the usual case) GP_ALPHA on the other copy
+  GPOperands G;
+  int gcp = -1;
+  if (SPEC && sd.c.pending) {
+    if (sd.c.phase == PH_GP_ALPHA) gcp = sd.c.cur;
+    else if (sd.c.phase == PH_GP_TRIAL) gcp = sd.c.cur ^ 1;
+    if (gcp >= 0 && own) gp_prefetch(S, gcp, kk, G);
+  }
   if (sd.c.pending) {
     double R[kNP];
     sum_partials(slots, par, ntiles, sd.c.phase, f32_slots(mixed, sd.c.phase), pf, R);
@@ -999,6 +1097,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
         acc[0] = (double)gam;
         acc[1] = (double)del;
       }
+    } else if (SPEC && gcp == sd.c.cur && (phase == PH_GP_ALPHA || phase == PH_GP_TRIAL)) {
+      gp_pass_prefetched(S, sd.c, phase, kk, own, G, acc);
     } else {
       run_pass<CT, PRE>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
     }

@@ -428,11 +428,11 @@ namespace {
 // Tuned configurations by operator shape and precision, shared by the handles
 // of the process (handles created with automatic options start from them).
 struct TuneKey {
-  int kind, nx, ny, mixed, list, precond;
+  int kind, nx, ny, mixed, list, precond, tile;
   int64_t n, nnz;
   bool operator<(const TuneKey &o) const {
-    return std::tie(kind, nx, ny, mixed, list, precond, n, nnz) <
-           std::tie(o.kind, o.nx, o.ny, o.mixed, o.list, o.precond, o.n, o.nnz);
+    return std::tie(kind, nx, ny, mixed, list, precond, tile, n, nnz) <
+           std::tie(o.kind, o.nx, o.ny, o.mixed, o.list, o.precond, o.tile, o.n, o.nnz);
   }
 };
 std::mutex g_tune_mu;
@@ -462,7 +462,8 @@ namespace {
 
 TuneKey tune_key(const gpcg_handle_s *h) {
   return TuneKey{h->op.kind, h->st.nx, h->st.ny, h->st.mixed, h->st.list ? 1 : 0,
-                 h->st.dinv ? 1 : 0, h->st.n, h->op.kind == GPCG_OP_CSR ? h->op.nnz : 0};
+                 h->st.dinv ? 1 : 0, h->st.tile, h->st.n,
+                 h->op.kind == GPCG_OP_CSR ? h->op.nnz : 0};
 }
 
 void fill_static(gpcg_handle_s *h) {
@@ -633,6 +634,8 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
     auto it = g_tuned.find(tune_key(h));
     if (it != g_tuned.end()) h->cfg = it->second;
   }
+  // early operand loads need a stencil QP with one unknown per thread
+  if (!spec_ok(h->st)) h->cfg.spec = 0;
   if (hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(GPCG_ERR_HIP, "hipEventCreate failed"));

@@ -65,3 +65,20 @@ def test_batch_autotune_keeps_the_answer():
     bt.close()
     for s in solvers:
         s.close()
+
+
+def test_tuned_configuration_respects_other_tile_sizes():
+    """A configuration tuned for 256-unknown tiles (with early operand loads)
+    is not applied to a handle with wider tiles of the same operator."""
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    inst = instances.obstacle(69, 8, amplitude=0.45)
+    s = gpcg.Solver(G.operator_for(inst), device=dev)
+    b, l, u, x0 = (G.to_dev(a) for a in (inst.b, inst.l, inst.u, inst.x0))
+    rep = s.autotune(b, l, u, x0)
+    assert rep["mismatches"] == 0
+    s.close()
+    x256, _, _ = G.solve(inst)
+    x512, _, st = G.solve(inst, tile=512)
+    assert st["status"] == gpcg.GPCG_OK, st
+    assert G.rel_inf(x512, x256) <= 1e-9
