@@ -245,6 +245,9 @@ typedef struct {
   int32_t tiles_per_wg; /* split form: tiles per data workgroup              */
   int32_t prefetch;     /* 1: CG operands loaded before the state is read    */
   int32_t chunk;        /* passes per graph replay                           */
+  int32_t shrink;       /* stepped batch: the launch is re-formed over the
+                           unfinished QPs once 1/shrink of its tiles are done */
+  int32_t pad;
   double ms;            /* wall time of one solve                            */
 } gpcg_tune_entry;
 
@@ -288,8 +291,10 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace,
 int gpcg_batch_solve(gpcg_batch bt, const gpcg_problem *probs, int mode, gpcg_stats *stats);
 
 /* Autotuner of the stepped batch form (see gpcg_autotune): tiles per data
- * workgroup (1, 2, 4), early CG operand loads and passes per graph replay,
- * each candidate timed on a full stepped solve of the batch.  x0s[i] (device,
+ * workgroup (1, 2, 4), early CG operand loads, passes per graph replay and
+ * the schedule (the launch is re-formed over the unfinished QPs once 1/3,
+ * 1/6 or 1/12 of its tiles are done), each candidate timed on a full stepped
+ * solve of the batch.  x0s[i] (device,
  * read only) is copied into probs[i].x before every candidate; probs[i].x
  * receives the answer.  The choice is kept by the batch. */
 int gpcg_batch_autotune(gpcg_batch bt, const gpcg_problem *probs, const double *const *x0s,

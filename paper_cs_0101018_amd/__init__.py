@@ -99,7 +99,8 @@ GPCG_TUNE_MAX = 32
 
 class gpcg_tune_entry(C.Structure):
     _fields_ = [("form", C.c_int32), ("tiles_per_wg", C.c_int32), ("prefetch", C.c_int32),
-                ("chunk", C.c_int32), ("ms", C.c_double)]
+                ("chunk", C.c_int32), ("shrink", C.c_int32), ("pad", C.c_int32),
+                ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

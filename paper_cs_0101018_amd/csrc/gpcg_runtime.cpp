@@ -416,9 +416,10 @@ struct LaunchCfg {
   int tiles_per_wg;  // split form: consecutive tiles per data workgroup
   int spec;          // CG operands loaded before the state is known (stencils)
   int chunk;         // passes per graph replay / host check (even)
+  int shrink = 3;    // stepped batch: re-form the launch once 1/shrink of its tiles are done
   bool operator==(const LaunchCfg &o) const {
     return split == o.split && tiles_per_wg == o.tiles_per_wg && spec == o.spec &&
-           chunk == o.chunk;
+           chunk == o.chunk && shrink == o.shrink;
   }
   bool operator!=(const LaunchCfg &o) const { return !(*this == o); }
 };
@@ -755,6 +756,7 @@ void note(gpcg_tune_report *r, const LaunchCfg &c, double ms) {
   e.tiles_per_wg = c.tiles_per_wg;
   e.prefetch = c.spec;
   e.chunk = c.chunk;
+  e.shrink = c.shrink;
   e.ms = ms;
 }
 
@@ -1025,7 +1027,7 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->items = (WgItem *)(b->ws + items_offset(count));
   b->tbytes = need;
   b->mixed = handles[0]->st.mixed;
-  b->cfg = LaunchCfg{1, 1, 1, default_chunk(handles[0]->opt)};
+  b->cfg = LaunchCfg{1, 1, 1, default_chunk(handles[0]->opt), 3};
   int rc = alloc_flag(&b->flags, (size_t)count);
   if (rc) {
     delete b;
@@ -1135,12 +1137,12 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
       if (rc) return rc;
-      // run until at least a third of this launch's tiles belong to finished QPs
+      // run until 1/shrink of this launch's tiles belong to finished QPs
       auto enough = [&]() {
         int done_tiles = 0;
         for (int i : active)
           if (b->flags.host[i]) done_tiles += b->hs[i]->st.ntiles;
-        return 3 * done_tiles >= total;
+        return (int64_t)b->cfg.shrink * done_tiles >= total;
       };
       rc = run_until(b->stream, SL, b->mixed, spec, 1, chunk, graph, b->ev, enough, (int64_t)1 << 26,
                      &launches, &checks);
@@ -1240,6 +1242,11 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     c.chunk = ch;
     if ((rc = consider(c)) < 0) return rc;
   }
+  for (int sh : {3, 6, 12}) {
+    LaunchCfg c = best;
+    c.shrink = sh;
+    if ((rc = consider(c)) < 0) return rc;
+  }
   b->cfg = best;
   if (report) {
     report->mismatches = mismatches;
@@ -1247,6 +1254,7 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     report->chosen.tiles_per_wg = best.tiles_per_wg;
     report->chosen.prefetch = best.spec;
     report->chosen.chunk = best.chunk;
+    report->chosen.shrink = best.shrink;
     report->chosen.ms = best_ms;
   }
   if (mismatches) return fail(GPCG_ERR_HIP, "batch autotune: launch configurations disagreed");
