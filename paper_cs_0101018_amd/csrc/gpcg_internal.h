@@ -6,11 +6,11 @@
 // over the unknowns of a QP (the initial projection and gradient, the exact
 // step length of a gradient-projection iterate, a trial point of a projected
 // search fused with the gradient at that point, the set-up of a reduced CG
-// solve, one CG iteration).  Each workgroup reduces its tile into a fixed
-// slot of `partials`.  The NEXT launch starts with every workgroup summing
-// those slots in tile order and running the scalar transition itself; all
-// workgroups reach identical decisions, no atomics are needed, and the kernel
-// boundary is the only barrier.  The state and the slots are double-buffered
+// solve, one CG iteration).  Each workgroup reduces its 256-unknown tile into
+// a fixed tile slot.  Before the next pass the slots are summed in tile order
+// and the scalar transition picks the next pass: in every workgroup of the
+// next launch (fused form) or in a transition kernel (split form).  The
+// kernel boundary is the barrier; the state and the slots are double-buffered
 // by launch parity.
 #pragma once
 

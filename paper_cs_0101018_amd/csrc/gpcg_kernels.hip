@@ -10,20 +10,25 @@
 //   GP_TRIAL  y' = P[y - alpha g], g' = Ay' - b, written to the spare copies of
 //             x and g; g's, s'As, active-set changes, face of y'.  Accepting
 //             the step (eq. (gplsstop)) is a flip of the current copy.
-//   CG_INIT   free mask, rho = -g on F, u = A rho, w = 0  (eqs. (cg), (cg2))
+//   CG_INIT   free mask, rho = -g on F, z = M^-1 rho, u = A z, w = 0
+//             (eqs. (cg), (cg2); M = I, or diag(A) with the Jacobi option)
+//   CG_LIST   list form only: compact the free mask into an index list
 //   CG_ITER   one CG iteration in the single-reduction form of Chronopoulos
-//             and Gear: p, s = Ap by recurrence, w, rho, u = A rho, rho'rho,
-//             rho'u (eq. (cgstop1) uses 1/2 alpha rho'rho)
+//             and Gear: s = Ap and p by recurrence, w, rho, z, u = A z, and
+//             the two sums rho'z, z'u (eq. (cgstop1) uses 1/2 alpha rho'z)
 //   PS_TRIAL  x' = P[x + alpha w], g' = Ax' - b, g's, s'As, face of x'
 //             (eq. (cglsstop2)); acceptance is again a flip.
-// Reductions are deterministic: wave64 butterflies and LDS per tile into a
-// fixed slot, then a fixed-order sum over the slots.  The stepped form sums
-// the slots of the previous launch in every workgroup and runs the scalar
-// transition redundantly (identical inputs, identical decisions), so the
-// kernel boundary is the only barrier and no atomics are used.
+// Reductions are deterministic: wave64 DPP butterflies and LDS per 256-unknown
+// tile into a fixed slot, then a fixed-order sum over the slots.  Launch
+// forms: fused (every workgroup sums the previous pass's slots and runs the
+// scalar transition redundantly -- identical inputs, identical decisions --
+// then its tile of the next pass), split (a transition kernel, then a lean
+// data kernel) and persistent (one cooperative launch, per-QP counter
+// barriers).  All three use the same tiles and summation orders, so a QP gets
+// bitwise the same answer in each.
 //
-// No MFMA: nothing on this path is a dense contraction; memory traffic bounds
-// every pass.
+// No MFMA: nothing on this path is a dense contraction; memory traffic and
+// latency bound every pass.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
