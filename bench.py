@@ -418,6 +418,8 @@ def main():
                     help="preconditioner of the reduced CG")
     ap.add_argument("--cg-stop", default="decrease", choices=["decrease", "residual"],
                     help="CG stopping test: relative decrease (the paper's) or residual")
+    ap.add_argument("--lookahead", default="auto", choices=["auto", "on", "off"],
+                    help="fused form: trial passes also evaluate the next step length")
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
                     help="free set of the reduced CG: byte mask or compacted list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -477,8 +479,11 @@ def main():
           "off": gpcg.GPCG_PREFETCH_OFF}[args.prefetch]
     pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
     cs = gpcg.GPCG_CGSTOP_RESIDUAL if args.cg_stop == "residual" else gpcg.GPCG_CGSTOP_DECREASE
+    la = {"auto": gpcg.GPCG_LOOKAHEAD_AUTO, "on": gpcg.GPCG_LOOKAHEAD_ON,
+          "off": gpcg.GPCG_LOOKAHEAD_OFF}[args.lookahead]
     solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf, precond=pc,
-                         cg_stop=cs, tiles_per_wg=args.tiles_per_wg, chunk=args.chunk, **opts)
+                         cg_stop=cs, lookahead=la, tiles_per_wg=args.tiles_per_wg,
+                         chunk=args.chunk, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
 
@@ -551,7 +556,7 @@ def main():
                    "free_set": args.free_set, "form": args.form,
                    "tiles_per_wg": args.tiles_per_wg, "prefetch": args.prefetch,
                    "precond": args.precond, "cg_stop": args.cg_stop,
-                   "chunk": args.chunk,
+                   "lookahead": args.lookahead, "chunk": args.chunk,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
         "roofline": {
@@ -571,7 +576,8 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile([s["ms_total"] for s in stats], 50)), 3),
                        "p99": round(float(np.percentile([s["ms_total"] for s in stats], 99)), 3)},
         "solve": {k: st[k] for k in ("outer_iters", "gp_iters", "cg_iters", "backtracks",
-                                     "face_repeats", "passes", "launches", "pg", "tau")},
+                                     "face_repeats", "passes", "lookaheads", "launches", "pg",
+                                     "tau")},
         "phase_ms": {k: round(st[k], 3) for k in ("ms_cg", "ms_gp", "ms_search", "ms_other")},
     }
     if args.extras:

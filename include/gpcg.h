@@ -130,6 +130,14 @@ typedef struct {
                           stencil has a constant diagonal, which leaves the
                           iterates unchanged: there it is not applied      */
   int32_t cg_stop;      /* GPCG_CGSTOP_DECREASE (default) or _RESIDUAL       */
+  int32_t lookahead;    /* fused form, stencil operators, 256-unknown tiles:
+                          the pass that evaluates a trial point of the
+                          gradient-projection search also evaluates eq.
+                          (bqpls) at it, the step length of the next iterate,
+                          which then needs no pass of its own:
+                          GPCG_LOOKAHEAD_AUTO (on), _ON (the same) or _OFF.
+                          x and every count but the passes are bitwise the
+                          same either way                                    */
 } gpcg_options;
 
 #define GPCG_PRECOND_NONE 0
@@ -138,6 +146,10 @@ typedef struct {
 #define GPCG_CGSTOP_RESIDUAL 1 /* ||r_k + A_k w_j|| <= eta_2 ||r_k||, the standard
                                   test the paper contrasts with eq. (cgstop1)
                                   (M^-1 norm when preconditioned)               */
+
+#define GPCG_LOOKAHEAD_AUTO 0
+#define GPCG_LOOKAHEAD_ON 1
+#define GPCG_LOOKAHEAD_OFF 2
 
 #define GPCG_PREFETCH_AUTO 0
 #define GPCG_PREFETCH_ON 1
@@ -153,7 +165,8 @@ typedef struct {
  * eta2_reduce 0.1, mu 0.01, max_outer 100000, max_gp 50, max_backtrack 60,
  * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
  * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO,
- * precond GPCG_PRECOND_NONE, cg_stop GPCG_CGSTOP_DECREASE. */
+ * precond GPCG_PRECOND_NONE, cg_stop GPCG_CGSTOP_DECREASE,
+ * lookahead GPCG_LOOKAHEAD_AUTO. */
 void gpcg_options_default(gpcg_options *opt);
 
 /* ------------------------------------------------------------------- stats */
@@ -170,6 +183,9 @@ typedef struct {
   double q;              /* q(x) at the answer                                */
   int64_t n_free, n_lower, n_upper; /* face of the answer (fixed vars: lower) */
   int64_t passes;        /* device passes executed                            */
+  int64_t lookaheads;    /* gradient-projection step lengths evaluated by the
+                            trial pass before them (no pass of their own):
+                            passes + lookaheads is the same in every form    */
   int64_t launches;      /* kernel launches issued (including no-op tails)    */
   int64_t host_checks;   /* host waits on device progress                     */
   double bytes;          /* algorithmic HBM bytes of all passes               */

@@ -40,6 +40,7 @@ GPCG_FORM_AUTO, GPCG_FORM_FUSED, GPCG_FORM_SPLIT = 0, 1, 2
 GPCG_PREFETCH_AUTO, GPCG_PREFETCH_ON, GPCG_PREFETCH_OFF = 0, 1, 2
 GPCG_PRECOND_NONE, GPCG_PRECOND_JACOBI = 0, 1
 GPCG_CGSTOP_DECREASE, GPCG_CGSTOP_RESIDUAL = 0, 1
+GPCG_LOOKAHEAD_AUTO, GPCG_LOOKAHEAD_ON, GPCG_LOOKAHEAD_OFF = 0, 1, 2
 
 
 class gpcg_operator(C.Structure):
@@ -56,7 +57,7 @@ class gpcg_options(C.Structure):
                 ("tile", C.c_int32), ("chunk", C.c_int32), ("use_graph", C.c_int32),
                 ("max_stall", C.c_int32), ("form", C.c_int32),
                 ("tiles_per_wg", C.c_int32), ("prefetch", C.c_int32),
-                ("precond", C.c_int32), ("cg_stop", C.c_int32)]
+                ("precond", C.c_int32), ("cg_stop", C.c_int32), ("lookahead", C.c_int32)]
 
 
 class gpcg_stats(C.Structure):
@@ -65,7 +66,8 @@ class gpcg_stats(C.Structure):
                 ("cg_phases", C.c_int32), ("x0_projected", C.c_int32), ("pg0", C.c_double),
                 ("pg", C.c_double), ("tau", C.c_double), ("q", C.c_double),
                 ("n_free", C.c_int64), ("n_lower", C.c_int64), ("n_upper", C.c_int64),
-                ("passes", C.c_int64), ("launches", C.c_int64), ("host_checks", C.c_int64),
+                ("passes", C.c_int64), ("lookaheads", C.c_int64), ("launches", C.c_int64),
+                ("host_checks", C.c_int64),
                 ("bytes", C.c_double), ("ms_total", C.c_double), ("ms_cg", C.c_double),
                 ("ms_gp", C.c_double), ("ms_search", C.c_double), ("ms_other", C.c_double)]
 

@@ -19,7 +19,7 @@
 namespace gpcg {
 
 constexpr int kBlock = 256;   // threads per workgroup (four wave64s)
-constexpr int kNP = 8;        // reduction slots per tile and pass
+constexpr int kNP = 10;       // reduction slots per tile and pass
 
 enum Phase : int32_t {
   PH_INIT = 0,    // x <- mid(l, u, x0); g <- Ax - b; checks; P grad q norm; face counts
@@ -46,7 +46,8 @@ struct QPStatic {
   int32_t max_backtrack, max_cg, max_stall, cg_stop;  // cg_stop: 0 eq. (cgstop1), 1 residual
   int64_t n;
   uint64_t div_magic;  // k / nx == (k * div_magic) >> div_shift for k < 2^30
-  int32_t div_shift, pad1;
+  int32_t div_shift;
+  int32_t gp_la;  // fused form: GP_TRIAL also sums eq. (bqpls) at the trial point
   double w;  // constant stencil weight
   float w32, pad2;
   const double *wx, *wy;     // edge weights (FP64)
@@ -77,6 +78,7 @@ struct QPCore {
   double eta, cg_alpha, cg_beta, gamma, cg_decmax, gamma0;
   int64_t m_free, n_lower, n_upper, n_nonbinding;
   int64_t passes, cg_free_rows;
+  int64_t lookaheads;  // eq. (bqpls) evaluated inside a trial pass
 };
 
 // One copy of the state per launch parity: the core plus per-pass counters.

@@ -347,7 +347,7 @@ __device__ __forceinline__ void sum_partials(const double *slots, int par, int n
   if (ntiles > kBlock) {
     if (ns == 2) sum_slot_tail<2, DEEP ? 40 : 4>(slots, par, ntiles, res, vf);
     else if (ns == 3) sum_slot_tail<3, DEEP ? 24 : 4>(slots, par, ntiles, res, vf);
-    else sum_slot_tail<kNP, DEEP ? 8 : 2>(slots, par, ntiles, res, vf);
+    else sum_slot_tail<kNP, DEEP ? 6 : 2>(slots, par, ntiles, res, vf);
   }
   block_slots(ns, f32, res, vf);
 }
@@ -366,10 +366,179 @@ __device__ __forceinline__ void face_acc(double x, double l, double u, double g,
   acc[4] = __fma_rn(x, g - b, acc[4]);
 }
 
+// GP_TRIAL of a stencil QP that also evaluates the step length of the next
+// gradient-projection iterate (eq. (bqpls) at the trial point y'), so that
+// the phase needs no separate GP_ALPHA pass.  Per chunk of 256 unknowns
+// [c0, c0 + 256) the workgroup forms, in LDS, y' on the five grid rows at
+// offsets -2 nx .. 2 nx from the chunk (the middle rows one and two entries
+// wider), g' = Ay' - b and d' = P grad q(y') on the chunk and the rows next to
+// it, and finally (A d')_k on the chunk: slots 8 and 9 receive d'd' and
+// d'Ad'.  Every value is the expression its owner evaluates in a GP_TRIAL
+// pass and then in a GP_ALPHA pass, so the sums are bitwise those two passes'.
+constexpr int kLaW = kBlock + 4;  // LDS row: positions c0 - 2 .. c0 + 257
+
+// The stencil row of apply_row / apply_row2 on values at (k, W, E, S, N).
+__device__ __forceinline__ double row5(const QPStatic *S, const double *wt, const bool *has,
+                                       double c, double vW, double vE, double vS, double vN) {
+  vW = has[0] ? vW : 0.0;
+  vE = has[1] ? vE : 0.0;
+  vS = has[2] ? vS : 0.0;
+  vN = has[3] ? vN : 0.0;
+  if (S->op_kind == OPK_CONST) return S->w * ((c - vW) + (c - vE) + ((c - vS) + (c - vN)));
+  return (wt[0] * (c - vW) + wt[1] * (c - vE)) + (wt[2] * (c - vS) + wt[3] * (c - vN));
+}
+
+// Grid coordinates of unknown p and which of its W, E, S, N neighbours exist.
+__device__ __forceinline__ void grid_has(const QPStatic *S, int64_t p, int32_t &i, int32_t &j,
+                                         bool (&has)[4]) {
+  const int32_t nx = S->nx;
+  j = (int32_t)(((uint64_t)p * S->div_magic) >> S->div_shift);
+  i = (int32_t)(p - (int64_t)j * nx);
+  has[0] = i > 0;
+  has[1] = i < nx - 1;
+  has[2] = j > 0;
+  has[3] = j < S->ny - 1;
+}
+
+__device__ __forceinline__ void stencil_weights(const QPStatic *S, int64_t p, int32_t i,
+                                                int32_t j, double (&wt)[4]) {
+  if (S->op_kind == OPK_VAR) {
+    const int64_t ex = (int64_t)j * (S->nx + 1) + i;
+    wt[0] = S->wx[ex];
+    wt[1] = S->wx[ex + 1];
+    wt[2] = S->wy[p];
+    wt[3] = S->wy[p + S->nx];
+  }
+}
+
+// Global operands of a look-ahead trial pass over the 256 unknowns from c0,
+// thread t: x, l, u, g (copy cp) at c0 + t + r nx on the rows r = -2..2; the
+// same at one entry beyond the chunk's columns (threads t < 8, entry
+// la_edge(t)); b, the neighbour flags and the edge weights at the middle-row
+// entries (and at the middle-row end of threads 1 and 2).  All loads are
+// issued together, before any of them is used.
+struct LAOperands {
+  double x[5], l[5], u[5], g[5];
+  double xe, le, ue, ge;
+  double b[4], wt[4][4];  // [0..2]: rows -1, 0, 1 at column t; [3]: the row end
+  bool has[4][4];
+};
+
+// Entry beyond the chunk's columns taken by thread t < 8, as (row, column -
+// c0): (0, -2), (0, -1), (0, 256), (0, 257), (-1, -1), (-1, 256), (1, -1),
+// (1, 256).  Threads 1 and 2 hold the two ends of the middle row.
+__device__ __forceinline__ void la_edge(int t, int &r, int &q) {
+  r = t < 4 ? 0 : (t < 6 ? -1 : 1);
+  q = t < 4 ? (t < 2 ? t - 2 : kBlock + t - 2) : ((t & 1) ? kBlock : -1);
+}
+
+__device__ __forceinline__ void la_load(const QPStatic *__restrict__ S, int cp, int64_t c0,
+                                        LAOperands &O) {
+  const int64_t n = S->n, nx = S->nx;
+  const double *__restrict__ x = S->x[cp];
+  const double *__restrict__ g = S->g[cp];
+  const int t = (int)threadIdx.x;
+#pragma unroll
+  for (int r = -2; r <= 2; ++r) {
+    const int64_t p = c0 + t + r * nx;
+    const bool in = p >= 0 && p < n;
+    O.x[r + 2] = in ? x[p] : 0.0;
+    O.l[r + 2] = in ? S->l[p] : 0.0;
+    O.u[r + 2] = in ? S->u[p] : 0.0;
+    O.g[r + 2] = in ? g[p] : 0.0;
+  }
+  int er, eq;
+  la_edge(t, er, eq);
+  const int64_t pe = c0 + eq + er * nx;
+  const bool ine = t < 8 && pe >= 0 && pe < n;
+  O.xe = ine ? x[pe] : 0.0;
+  O.le = ine ? S->l[pe] : 0.0;
+  O.ue = ine ? S->u[pe] : 0.0;
+  O.ge = ine ? g[pe] : 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int64_t p = m < 3 ? c0 + t + (m - 1) * nx : pe;
+    const bool in = m < 3 ? (p >= 0 && p < n) : (ine && (t == 1 || t == 2));
+    int32_t i = 0, j = 0;
+    if (in) grid_has(S, p, i, j, O.has[m]);
+    else
+      for (int e = 0; e < 4; ++e) O.has[m][e] = false;
+    O.b[m] = in ? S->b[p] : 0.0;
+    if (S->op_kind == OPK_VAR && in) stencil_weights(S, p, i, j, O.wt[m]);
+    else
+      for (int e = 0; e < 4; ++e) O.wt[m][e] = 0.0;
+  }
+}
+
+// The pass on loaded operands (copy cp in, copy cp ^ 1 out; chunk [c0, k1)).
+__device__ __forceinline__ void la_compute(const QPStatic *__restrict__ S, int cp, double a,
+                                           int64_t c0, int64_t k1, const LAOperands &O,
+                                           double (&acc)[kNP]) {
+  __shared__ double s_y[5][kLaW];  // y' on rows -2..2, entry pos - c0 + 2
+  __shared__ double s_s[3][kLaW];  // y' - x on rows -1..1
+  __shared__ double s_d[3][kLaW];  // d' on rows -1..1
+  const int64_t n = S->n, nx = S->nx;
+  const int t = (int)threadIdx.x;
+  // y' and y' - x on the five rows and at the entry beyond the columns
+#pragma unroll
+  for (int r = -2; r <= 2; ++r) {
+    const double yv = gp_point(O.x[r + 2], O.l[r + 2], O.u[r + 2], O.g[r + 2], a);
+    s_y[r + 2][t + 2] = yv;
+    if (r >= -1 && r <= 1) s_s[r + 1][t + 2] = yv - O.x[r + 2];
+  }
+  int er, eq;
+  la_edge(t, er, eq);
+  if (t < 8) {
+    const double yv = gp_point(O.xe, O.le, O.ue, O.ge, a);
+    s_y[er + 2][eq + 2] = yv;
+    s_s[er + 1][eq + 2] = yv - O.xe;
+  }
+  __syncthreads();
+  // g' = Ay' - b and d' = P grad q(y') on the middle rows and at the ends of
+  // the middle row; the trial pass proper at the chunk's own unknown
+  const int64_t k = c0 + t;
+  auto grad_dir = [&](int m, int rr, int q, double yl, double yu) {
+    const int64_t p = c0 + q + rr * nx;
+    double dv = 0.0;
+    if (p >= 0 && p < n) {
+      const double yc = s_y[rr + 2][q + 2];
+      const double gy = row5(S, O.wt[m], O.has[m], yc, s_y[rr + 2][q + 1], s_y[rr + 2][q + 3],
+                             s_y[rr + 1][q + 2], s_y[rr + 3][q + 2]) -
+                        O.b[m];
+      dv = proj_grad(yc, yl, yu, gy);
+      if (m == 1 && k < k1) {
+        const double sk = s_s[1][t + 2];
+        const double As = row5(S, O.wt[1], O.has[1], sk, s_s[1][t + 1], s_s[1][t + 3],
+                               s_s[0][t + 2], s_s[2][t + 2]);
+        S->x[cp ^ 1][k] = yc;
+        S->g[cp ^ 1][k] = gy;
+        face_acc(yc, yl, yu, gy, O.b[1], acc);
+        acc[5] = __fma_rn(O.g[2], sk, acc[5]);
+        acc[6] = __fma_rn(sk, As, acc[6]);
+        acc[7] += (is_active(yc, yl, yu) != is_active(O.x[2], yl, yu)) ? 1.0 : 0.0;
+      }
+    }
+    s_d[rr + 1][q + 2] = dv;
+  };
+  grad_dir(0, -1, t, O.l[1], O.u[1]);
+  grad_dir(1, 0, t, O.l[2], O.u[2]);
+  grad_dir(2, 1, t, O.l[3], O.u[3]);
+  if (t == 1 || t == 2) grad_dir(3, 0, eq, O.le, O.ue);
+  __syncthreads();
+  // (A d')_k on the chunk
+  if (k < k1) {
+    const double dk = s_d[1][t + 2];
+    const double Adk = row5(S, O.wt[1], O.has[1], dk, s_d[1][t + 1], s_d[1][t + 3],
+                            s_d[0][t + 2], s_d[2][t + 2]);
+    acc[8] = __fma_rn(dk, dk, acc[8]);
+    acc[9] = __fma_rn(dk, Adk, acc[9]);
+  }
+}
+
 // One pass over the unknowns [k0, k1) of a tile (the list entries [k0, k1)
 // for a CG iteration of the list form).  `slots` are the QP's tile slots: the
 // list pass reads the free counts the set-up pass left at parity lpar.
-template <typename CT, bool PRE>
+template <typename CT, bool PRE, bool LA>
 __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restrict__ slots,
                          const QPCore &d, int phase, int lpar, int64_t k0, int64_t k1,
                          double (&acc)[kNP], float (&accf)[2]) {
@@ -414,6 +583,12 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       }
     } break;
     case PH_GP_TRIAL: {
+      if (LA && S->gp_la) {  // 256-unknown tiles: one chunk
+        LAOperands O;
+        la_load(S, d.cur, k0, O);
+        la_compute(S, d.cur, d.alpha, k0, k1, O, acc);
+        break;
+      }
       const OpView<double> A = op_view<double>(S);
       const double a = d.alpha;
       auto yv = [&](int64_t j) {
@@ -629,6 +804,19 @@ __device__ __forceinline__ void end_gp(const QPStatic *S, QPCore &d) {
   d.phase = PH_CG_INIT;
 }
 
+// The first trial of a gradient-projection iterate y, given dd = d'd and
+// dAd = d'Ad for d = P grad q(y).
+// Every field is written on both outcomes (selects, no branches), which keeps
+// the state in registers.
+__device__ __forceinline__ void gp_step(QPCore &d, double dd, double dAd) {
+  // P grad q(y) = 0: y solves the QP; d'Ad <= 0: A is not positive definite
+  const bool go = dd != 0.0 && dAd > 0.0;
+  d.status = go ? d.status : (dd == 0.0 ? (int32_t)GPCG_OK : (int32_t)GPCG_ERR_NOT_SPD);
+  d.alpha = go ? dd / dAd : d.alpha;  // eq. (bqpls): ||d||^2 / d'Ad
+  d.bt = go ? 0 : d.bt;
+  d.phase = go ? (int32_t)PH_GP_TRIAL : (int32_t)PH_DONE;
+}
+
 // Projected search along d_k = Z_k w: alpha = 1, 1/2, 1/4, ... (eq. cglsstop2).
 __device__ __forceinline__ void start_ps(QPCore &d) {
   d.alpha = 1.0;
@@ -646,8 +834,10 @@ __device__ __forceinline__ void set_face(QPCore &d, const double *R) {
 }
 
 // Folds the reduced results R of pass d.phase into the state and selects the
-// next pass.  Runs in one thread of every workgroup on identical inputs.
-__device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
+// next pass.  Runs in one thread of every workgroup on identical inputs.  la:
+// trial passes of this QP look ahead (slots 8 and 9 hold eq. (bqpls) at the
+// trial point; the fused form only).
+__device__ void transition(const QPStatic *S, QPCore &d, const double *R, bool la) {
   const int ph = d.phase;
   d.passes += 1;
   switch (ph) {
@@ -664,13 +854,7 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
       else start_gp(d);
       break;
     case PH_GP_ALPHA:
-      if (R[0] == 0.0) finish(d, GPCG_OK);  // P grad q(y) = 0: y solves the QP
-      else if (!(R[1] > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
-      else {
-        d.alpha = R[0] / R[1];  // eq. (bqpls): ||d||^2 / d'Ad
-        d.bt = 0;
-        d.phase = PH_GP_TRIAL;
-      }
+      gp_step(d, R[0], R[1]);
       break;
     case PH_GP_TRIAL: {
       const double gs = R[5], delta = gs + 0.5 * R[6];  // q(y') - q(y)
@@ -687,7 +871,12 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
         if (stop) end_gp(S, d);
         else {
           d.gp_j += 1;
-          d.phase = PH_GP_ALPHA;
+          if (la) {  // the trial pass looked ahead
+            d.lookaheads += 1;
+            gp_step(d, R[8], R[9]);
+          } else {
+            d.phase = PH_GP_ALPHA;
+          }
         }
       } else {
         d.alpha *= 0.5;
@@ -788,10 +977,10 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R) {
 // Runs the transition of the pending pass on a register copy of the core and
 // books the pass in the per-phase counters (thread 0, state in LDS).
 __device__ __forceinline__ void advance(const QPStatic *S, QPDyn &sd, const double *R,
-                                       uint64_t now) {
+                                       uint64_t now, bool la) {
   const int ph = sd.c.phase;
   QPCore c = sd.c;
-  transition(S, c, R);
+  transition(S, c, R, la);
   sd.c = c;
   if (ph >= 0 && ph < PH_COUNT) sd.pass_count[ph] += 1;
   const int bk = time_bucket(ph);
@@ -988,17 +1177,6 @@ __device__ __forceinline__ void gp_prefetch(const QPStatic *S, int cp, int64_t k
   }
 }
 
-// The stencil row of apply_row / apply_row2 on values at (k, W, E, S, N).
-__device__ __forceinline__ double row5(const QPStatic *S, const double *wt, const bool *has,
-                                       double c, double vW, double vE, double vS, double vN) {
-  vW = has[0] ? vW : 0.0;
-  vE = has[1] ? vE : 0.0;
-  vS = has[2] ? vS : 0.0;
-  vN = has[3] ? vN : 0.0;
-  if (S->op_kind == OPK_CONST) return S->w * ((c - vW) + (c - vE) + ((c - vS) + (c - vN)));
-  return (wt[0] * (c - vW) + wt[1] * (c - vE)) + (wt[2] * (c - vS) + wt[3] * (c - vN));
-}
-
 // GP_ALPHA and GP_TRIAL of run_pass on prefetched operands (one unknown per
 // thread, own: k is an unknown of the QP); the same formulas in the same
 // order, so the results are bitwise equal.
@@ -1066,7 +1244,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   // after GP_TRIAL (accepted, the usual case) GP_ALPHA on the other copy
   GPOperands G;
   int gcp = -1;
-  if (SPEC && sd.c.pending) {
+  if (SPEC && sd.c.pending && !S->gp_la) {
     if (sd.c.phase == PH_GP_ALPHA) gcp = sd.c.cur;
     else if (sd.c.phase == PH_GP_TRIAL) gcp = sd.c.cur ^ 1;
     if (gcp >= 0 && own) gp_prefetch(S, gcp, kk, G);
@@ -1075,7 +1253,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     double R[kNP];
     sum_partials(slots, par, ntiles, sd.c.phase, f32_slots(mixed, sd.c.phase), pf, R);
     if (threadIdx.x == 0) {
-      advance(S, sd, R, clk);
+      advance(S, sd, R, clk, S->gp_la != 0);
       sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
       s_fresh_done = sd.c.phase == PH_DONE;
     }
@@ -1105,7 +1283,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     } else if (SPEC && gcp == sd.c.cur && (phase == PH_GP_ALPHA || phase == PH_GP_TRIAL)) {
       gp_pass_prefetched(S, sd.c, phase, kk, own, G, acc);
     } else {
-      run_pass<CT, PRE>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT, PRE, true>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
     }
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     __syncthreads();
@@ -1145,7 +1323,7 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
     double R[kNP];
     sum_partials<true>(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
     if (threadIdx.x == 0) {
-      advance(S, sd, R, clk);
+      advance(S, sd, R, clk, false);
       sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
       s_fresh_done = sd.c.phase == PH_DONE;
     }
@@ -1233,7 +1411,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     float accf[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-    run_pass<CT, PRE>(S, slots, sc, phase, par, k0, k1, acc, accf);
+    run_pass<CT, PRE, false>(S, slots, sc, phase, par, k0, k1, acc, accf);
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
   }
@@ -1273,7 +1451,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
       double R[kNP], pf[kNP];
       prefetch_slot(slots, par, pf);
       sum_partials(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
-      if (threadIdx.x == 0) advance(S, sd, R, wall_clock64());
+      if (threadIdx.x == 0) advance(S, sd, R, wall_clock64(), false);
       __syncthreads();
     }
     const int phase = sd.c.phase;
@@ -1285,7 +1463,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
       float accf[2] = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-      run_pass<CT, PRE>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT, PRE, false>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
       write_partial(slots, par ^ 1, phase, f32_slots(S->mixed, phase), tile, acc, accf);
       __syncthreads();
     }

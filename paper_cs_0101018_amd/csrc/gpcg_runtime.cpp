@@ -109,6 +109,8 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "unknown preconditioner");
   if (o->cg_stop != GPCG_CGSTOP_DECREASE && o->cg_stop != GPCG_CGSTOP_RESIDUAL)
     return fail(GPCG_ERR_ARG, "unknown CG stopping test");
+  if (o->lookahead < GPCG_LOOKAHEAD_AUTO || o->lookahead > GPCG_LOOKAHEAD_OFF)
+    return fail(GPCG_ERR_ARG, "unknown lookahead mode");
   return GPCG_OK;
 }
 
@@ -291,6 +293,7 @@ void fill_stats(const QPStatic &s, const QPDyn &dy, double tick_hz, gpcg_stats *
   st->n_upper = d.n_upper;
   st->n_free = s.n - d.n_lower - d.n_upper;
   st->passes = d.passes;
+  st->lookaheads = d.lookaheads;
   st->bytes = solve_bytes(s, dy);
   const double ms = 1e3 / tick_hz;
   st->ms_cg = dy.t_bucket[TB_CG] * ms;
@@ -514,7 +517,7 @@ void fill_static(gpcg_handle_s *h) {
 
 // Uploads the state of a new solve of handle h (not yet started).
 int upload_solve(gpcg_handle_s *h, const double *b, const double *l, const double *u, double *x,
-                 int32_t *flag_dev, hipStream_t stream) {
+                 int32_t *flag_dev, bool fused, hipStream_t stream) {
   QPDev &q = *h->stage;
   std::memset(&q, 0, sizeof(q));
   q.st = h->st;
@@ -523,6 +526,12 @@ int upload_solve(gpcg_handle_s *h, const double *b, const double *l, const doubl
   q.st.u = u;
   q.st.x[0] = x;
   q.st.host_flag = flag_dev;
+  // trial passes look ahead in the fused form only (its kernel carries the
+  // code; the split form's lean data kernel keeps its register budget)
+  q.st.gp_la = (fused && h->st.op_kind != OPK_CSR && h->st.tile == kBlock &&
+                h->opt.lookahead != GPCG_LOOKAHEAD_OFF)
+                   ? 1
+                   : 0;
   initial_dyn(q.dyn[0]);
   initial_dyn(q.dyn[1]);
   HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPDev), hipMemcpyHostToDevice, stream));
@@ -573,6 +582,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->prefetch = GPCG_PREFETCH_AUTO;
   o->precond = GPCG_PRECOND_NONE;
   o->cg_stop = GPCG_CGSTOP_DECREASE;
+  o->lookahead = GPCG_LOOKAHEAD_AUTO;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {
@@ -684,7 +694,7 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   const double t0 = now_s();
   HIP_OK(hipStreamSynchronize(h->stream));  // the staging buffer may still be in flight
   h->flag.host[0] = 0;
-  int rc = upload_solve(h, b, l, u, x, h->flag.dev, h->stream);
+  int rc = upload_solve(h, b, l, u, x, h->flag.dev, !h->cfg.split, h->stream);
   if (rc) return rc;
   StepLaunch SL{};
   SL.single = h->dqp;
@@ -1071,7 +1081,7 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     gpcg_handle h = b->hs[i];
     HIP_OK(hipStreamSynchronize(h->stream));
     b->flags.host[i] = 0;
-    int rc = upload_solve(h, p.b, p.l, p.u, p.x, b->flags.dev + i, b->stream);
+    int rc = upload_solve(h, p.b, p.l, p.u, p.x, b->flags.dev + i, false, b->stream);
     if (rc) return rc;
   }
   auto **qp = (QPDev **)b->stage;

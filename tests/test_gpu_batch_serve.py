@@ -46,8 +46,10 @@ def test_batch_equals_alone(mode, mixed):
         xa, ga, sa = solo(inst, precision=mixed)
         assert st["status"] == sa["status"] == 0, (st, sa)
         assert np.array_equal(x, xa), inst.name
-        for k in ("outer_iters", "gp_iters", "cg_iters", "passes"):
+        for k in ("outer_iters", "gp_iters", "cg_iters"):
             assert st[k] == sa[k], (inst.name, k)
+        # batches never look ahead; a QP alone (fused form) may
+        assert st["passes"] == sa["passes"] + sa["lookaheads"], inst.name
 
 
 @pytest.mark.parametrize("mixed", [0, 1])
