@@ -366,25 +366,47 @@ int launch_chunk(hipStream_t stream, StepLaunch L, int mixed, int spec, int spli
   return GPCG_OK;
 }
 
-// Replays chunks until `done()` holds.  Keeps one chunk queued behind the one
-// the host waits on, so the GPU does not idle while the host checks.
+// Replays chunks until `done()` holds.  The next chunk is queued while the
+// running one still has a lead time left (its expected duration is that of
+// the chunk before it), so the GPU does not idle between chunks; queuing it
+// later than that would idle the GPU, queuing it earlier adds launches past
+// the last pass (they find the state done and return).  The lead is a fifth
+// of a chunk and at least four times what queuing a chunk costs the host.
 template <class Done>
 int run_until(hipStream_t stream, const StepLaunch &L, int mixed, int spec, int split, int chunk,
               hipGraphExec_t graph,
               hipEvent_t *ev, Done done, int64_t max_launches, int64_t *launches,
               int64_t *checks) {
+  double t_q = now_s();
   int rc = launch_chunk(stream, L, mixed, spec, split, chunk, graph);
   if (rc) return rc;
+  double t_start = now_s();  // the running chunk started no earlier than this
+  double submit = t_start - t_q;
+  double dur = 0.0;  // duration of the last finished chunk; 0 = not known yet
   *launches += chunk;
   HIP_OK(hipEventRecord(ev[0], stream));
   for (int64_t i = 1;; ++i) {
     if (*launches >= max_launches)
       return fail(GPCG_ERR_HANG, "device did not finish within the launch budget");
+    hipEvent_t prev = ev[(i - 1) & 1];
+    if (dur > 0.0) {  // hold the next chunk until the running one nears its end
+      const double lead = std::max(0.2 * dur, 4.0 * submit);
+      const double t_go = t_start + dur - lead;
+      while (now_s() < t_go && !done()) {
+        hipError_t e = hipEventQuery(prev);
+        if (e == hipSuccess) break;  // ended sooner than expected
+        if (e != hipErrorNotReady)
+          return fail(GPCG_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+        std::this_thread::yield();
+      }
+      if (done()) break;
+    }
+    t_q = now_s();
     rc = launch_chunk(stream, L, mixed, spec, split, chunk, graph);
     if (rc) return rc;
+    submit = 0.5 * submit + 0.5 * (now_s() - t_q);
     *launches += chunk;
     HIP_OK(hipEventRecord(ev[i & 1], stream));
-    hipEvent_t prev = ev[(i - 1) & 1];
     for (;;) {
       if (done()) break;
       hipError_t e = hipEventQuery(prev);
@@ -395,6 +417,10 @@ int run_until(hipStream_t stream, const StepLaunch &L, int mixed, int spec, int 
     }
     *checks += 1;
     if (done()) break;
+    // chunk i - 1 ended now; chunk i, queued before, starts now
+    const double t = now_s();
+    dur = t - t_start;
+    t_start = t;
   }
   HIP_OK(hipStreamSynchronize(stream));
   return GPCG_OK;
