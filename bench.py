@@ -418,6 +418,8 @@ def main():
                     help="preconditioner of the reduced CG")
     ap.add_argument("--cg-stop", default="decrease", choices=["decrease", "residual"],
                     help="CG stopping test: relative decrease (the paper's) or residual")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="unknowns per tile (multiple of 256; 0 = library choice)")
     ap.add_argument("--lookahead", default="auto", choices=["auto", "on", "off"],
                     help="fused form: trial passes also evaluate the next step length")
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
@@ -483,7 +485,7 @@ def main():
           "off": gpcg.GPCG_LOOKAHEAD_OFF}[args.lookahead]
     solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf, precond=pc,
                          cg_stop=cs, lookahead=la, tiles_per_wg=args.tiles_per_wg,
-                         chunk=args.chunk, **opts)
+                         chunk=args.chunk, tile=args.tile, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
 
@@ -556,7 +558,7 @@ def main():
                    "free_set": args.free_set, "form": args.form,
                    "tiles_per_wg": args.tiles_per_wg, "prefetch": args.prefetch,
                    "precond": args.precond, "cg_stop": args.cg_stop,
-                   "lookahead": args.lookahead, "chunk": args.chunk,
+                   "lookahead": args.lookahead, "chunk": args.chunk, "tile": args.tile,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
         "roofline": {

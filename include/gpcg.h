@@ -104,8 +104,12 @@ typedef struct {
   int32_t max_cg;      /* cap on CG iterations per phase; <= 0: m_k           */
   int32_t precision;   /* GPCG_PREC_*                                         */
   int32_t free_set;    /* GPCG_FREESET_*                                      */
-  int32_t tile;        /* unknowns per workgroup and pass (multiple of 256);
-                          0 = 256 (one unknown per thread)                    */
+  int32_t tile;        /* unknowns per tile, the unit of one reduction slot
+                          per pass (multiple of 256); 0 = library choice, a
+                          function of n only: 256 up to 262,144 unknowns,
+                          512 beyond.  The tile fixes the summation order:
+                          the answer depends on it, and on nothing else of
+                          the launch set-up                                   */
   int32_t chunk;       /* device passes per host check; 0 = library choice    */
   int32_t use_graph;   /* 1 = replay chunks as HIP graphs (default), 0 = launch */
   int32_t max_stall;   /* stop as GPCG_STAGNATED when ||P grad q|| after a

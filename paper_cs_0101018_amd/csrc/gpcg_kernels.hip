@@ -1381,16 +1381,21 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   const int mixed = S->mixed, ntiles = S->ntiles;
   double *slots = tile_slots(q);
   const int t1 = t0 + nt < ntiles ? t0 + nt : ntiles;
-  const bool lean = SPEC || (S->op_kind != OPK_CSR && S->list == nullptr && S->tile == kBlock);
+  const bool lean = SPEC || (S->op_kind != OPK_CSR && S->list == nullptr);
   if (phase == PH_CG_ITER && lean) {
+    // a tile of several 256-unknown chunks accumulates them in order, as
+    // run_pass does (thread t: unknowns k0 + t, k0 + t + 256, ...)
+    const int nchunk = S->tile / kBlock;
     for (int tile = t0; tile < t1; ++tile) {
-      if (!SPEC || tile != t0) {
-        kk = (int64_t)tile * kBlock + threadIdx.x;
-        own = kk < S->n;
-        if (own) cg_prefetch<CT, PRE>(S, par, kk, P);
-      }
       CT gam = CT(0), del = CT(0);
-      cg_iter_prefetched<CT, PRE>(S, sc, par, kk, own, P, gam, del);
+      for (int c = 0; c < nchunk; ++c) {
+        if (!SPEC || tile != t0 || c != 0) {
+          kk = (int64_t)tile * S->tile + (int64_t)c * kBlock + threadIdx.x;
+          own = kk < S->n;
+          if (own) cg_prefetch<CT, PRE>(S, par, kk, P);
+        }
+        cg_iter_prefetched<CT, PRE>(S, sc, par, kk, own, P, gam, del);
+      }
       double acc[kNP];
       float accf[2] = {(float)gam, (float)del};
 #pragma unroll

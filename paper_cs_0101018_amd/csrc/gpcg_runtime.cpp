@@ -114,14 +114,19 @@ int validate_opt(const gpcg_options *o) {
   return GPCG_OK;
 }
 
-// Unknowns per workgroup and pass: one per thread.  The same for every size
-// and every launch form, so a QP reduces in the same order alone, in a batch
-// or in the server.
-int tuned_tile(int64_t) { return kBlock; }
-
 // The fused form sums every tile slot of the previous pass in every
-// workgroup; beyond this many tiles the split form is cheaper.
+// workgroup; beyond this many 256-unknown tiles the split form is cheaper.
 constexpr int kFusedMaxTiles = 1024;
+
+// Unknowns per tile (one reduction slot per tile and pass): 256, one per
+// thread, up to 1024 x 256 unknowns; beyond that 512, which halves the slots
+// the transition of the split form sums.  Wider tiles save more slots but a
+// data workgroup sweeps the 256-unknown chunks of its tile one after the
+// other, and on the largest grids (1600^2 in FP64) 1024-unknown tiles lose
+// more there than they gain.  A function of n alone: a QP has the same tiles,
+// hence the same summation order and answer, alone, in a batch, in the server
+// and in every launch form.
+int tuned_tile(int64_t n) { return n > (int64_t)kFusedMaxTiles * kBlock ? 2 * kBlock : kBlock; }
 
 struct Layout {
   size_t qp, slots, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
@@ -661,7 +666,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   h->stage = (QPDev *)st;
   fill_static(h);
   h->cfg.split = o.form == GPCG_FORM_SPLIT ||
-                 (o.form == GPCG_FORM_AUTO && h->L.ntiles > kFusedMaxTiles);
+                 (o.form == GPCG_FORM_AUTO && h->st.n > (int64_t)kFusedMaxTiles * kBlock);
   h->cfg.tiles_per_wg = o.tiles_per_wg > 0 ? o.tiles_per_wg : 1;
   h->cfg.spec = spec_ok(h->st) && o.prefetch != GPCG_PREFETCH_OFF ? 1 : 0;
   h->cfg.chunk = default_chunk(o);
@@ -831,7 +836,7 @@ int gpcg_autotune(gpcg_handle h, const double *b, const double *l, const double 
   };
   // one dimension at a time: launch form, tiles per data workgroup, operand
   // prefetch, chunk length
-  if (h->L.ntiles <= 4 * kFusedMaxTiles) {
+  if (h->st.n <= (int64_t)4 * kFusedMaxTiles * kBlock) {
     LaunchCfg c = best;
     c.split = best.split ? 0 : 1;
     c.tiles_per_wg = 1;

@@ -57,7 +57,7 @@ def test_batch_equals_alone_many_tiles(mixed):
     """Members with more tiles than threads per workgroup (their slot sums
     have tails): the batch (split form) equals each one alone (fused form)."""
     insts = [instances.obstacle(300, 4, amplitude=0.4), instances.varcoef(270, 1),
-             instances.obstacle(45, 2)]
+             instances.obstacle(45, 2), instances.obstacle(560, 3)]  # 560^2: 512-unknown tiles
     xs, stats = _batch(insts, 0, precision=mixed)
     for inst, x, st in zip(insts, xs, stats):
         xa, ga, sa = solo(inst, precision=mixed)

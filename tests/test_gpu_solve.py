@@ -146,7 +146,8 @@ def test_deterministic_and_graph_invariant():
 
 
 @pytest.mark.parametrize("case", ["c0", "c0_csr", "c1s", "ragged_mixed", "ragged_csr_mixed",
-                                  "many_tiles", "many_tiles_mixed"])
+                                  "many_tiles", "many_tiles_mixed", "wide_auto_tiles",
+                                  "wide_auto_tiles_mixed"])
 def test_fused_and_split_forms_agree_bitwise(case):
     """The two launch forms use the same tiles and summation orders."""
     import paper_cs_0101018_amd as gpcg
@@ -159,6 +160,10 @@ def test_fused_and_split_forms_agree_bitwise(case):
         # more tiles than threads per workgroup: every slot sum has a tail
         "many_tiles": (instances.obstacle(601, 1), None, gpcg.GPCG_PREC_FP64),
         "many_tiles_mixed": (instances.varcoef(333, 2), None, gpcg.GPCG_PREC_MIXED),
+        # beyond 1024 x 256 unknowns the library's tiles hold several chunks
+        # of 256 (512 unknowns per tile)
+        "wide_auto_tiles": (instances.obstacle(1100, 2), None, gpcg.GPCG_PREC_FP64),
+        "wide_auto_tiles_mixed": (instances.varcoef(530, 4), None, gpcg.GPCG_PREC_MIXED),
     }[case]
     res = [G.solve(inst, kind, precision=prec, form=f)
            for f in (gpcg.GPCG_FORM_FUSED, gpcg.GPCG_FORM_SPLIT)]
