@@ -345,9 +345,9 @@ __device__ __forceinline__ void sum_partials(const double *slots, int par, int n
   vf[0] = mine ? (float)pf[0] : 0.0f;
   vf[1] = mine ? (float)pf[1] : 0.0f;
   if (ntiles > kBlock) {
-    if (ns == 2) sum_slot_tail<2, DEEP ? 40 : 4>(slots, par, ntiles, res, vf);
-    else if (ns == 3) sum_slot_tail<3, DEEP ? 24 : 4>(slots, par, ntiles, res, vf);
-    else sum_slot_tail<kNP, DEEP ? 6 : 2>(slots, par, ntiles, res, vf);
+    if (ns == 2) sum_slot_tail<2, DEEP ? 16 : 4>(slots, par, ntiles, res, vf);
+    else if (ns == 3) sum_slot_tail<3, DEEP ? 12 : 4>(slots, par, ntiles, res, vf);
+    else sum_slot_tail<kNP, DEEP ? 4 : 2>(slots, par, ntiles, res, vf);
   }
   block_slots(ns, f32, res, vf);
 }
@@ -1314,6 +1314,19 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   const double *slots = tile_slots(q);
   double pf[kNP];
   prefetch_slot(slots, par, pf);
+  // one QP (its tile count is a launch argument): the two slots a CG pass
+  // fills, of the tiles beyond the first 256, are loaded together with the
+  // state, before the pass that filled them is known
+  constexpr int kEarly = 20;  // tiles per thread: up to 21 x 256 tiles
+  const int nt = L.single ? L.total_tiles : 0;
+  const bool early = nt > kBlock && nt <= (kEarly + 1) * kBlock;
+  double e0[kEarly], e1[kEarly];
+#pragma unroll
+  for (int m = 0; m < kEarly; ++m) {
+    const int t = (int)threadIdx.x + (m + 1) * kBlock;
+    e0[m] = (early && t < nt) ? slots[slot_index(t, par, 0)] : 0.0;
+    e1[m] = (early && t < nt) ? slots[slot_index(t, par, 1)] : 0.0;
+  }
   const uint64_t clk = wall_clock64();
   copy_dyn(&q->dyn[par], &sd);
   copy_static(&q->st, &ss);
@@ -1321,7 +1334,29 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   const QPStatic *S = &ss;
   if (sd.c.pending) {
     double R[kNP];
-    sum_partials<true>(slots, par, S->ntiles, sd.c.phase, f32_slots(S->mixed, sd.c.phase), pf, R);
+    const int ph = sd.c.phase;
+    const bool f32 = f32_slots(S->mixed, ph);
+    if (early && nslots(ph) == 2) {
+      // the sum of sum_partials, in its order, on the early loads
+      float vf[2];
+      const bool mine = (int)threadIdx.x < nt;
+#pragma unroll
+      for (int k = 0; k < kNP; ++k) R[k] = (mine && k < 2) ? pf[k] : 0.0;
+      vf[0] = mine ? (float)pf[0] : 0.0f;
+      vf[1] = mine ? (float)pf[1] : 0.0f;
+#pragma unroll
+      for (int m = 0; m < kEarly; ++m) {
+        if ((int)threadIdx.x + (m + 1) * kBlock < nt) {
+          R[0] += e0[m];
+          R[1] += e1[m];
+          vf[0] += (float)e0[m];
+          vf[1] += (float)e1[m];
+        }
+      }
+      block_slots(2, f32, R, vf);
+    } else {
+      sum_partials<true>(slots, par, S->ntiles, ph, f32, pf, R);
+    }
     if (threadIdx.x == 0) {
       advance(S, sd, R, clk, false);
       sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
