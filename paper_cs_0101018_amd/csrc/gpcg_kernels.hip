@@ -9,7 +9,11 @@
 //   GP_ALPHA  d = P grad q(y): d'd, d'Ad (exact step, eq. (bqpls))
 //   GP_TRIAL  y' = P[y - alpha g], g' = Ay' - b, written to the spare copies of
 //             x and g; g's, s'As, active-set changes, face of y'.  Accepting
-//             the step (eq. (gplsstop)) is a flip of the current copy.
+//             the step (eq. (gplsstop)) is a flip of the current copy.  In the
+//             fused form the pass also looks ahead: d' = P grad q(y') on the
+//             tile and its neighbours (trial point two rows out, through LDS)
+//             gives d''d' and d''Ad', the next GP_ALPHA's sums, and that pass
+//             is skipped when the step is accepted and the phase goes on.
 //   CG_INIT   free mask, rho = -g on F, z = M^-1 rho, u = A z, w = 0
 //             (eqs. (cg), (cg2); M = I, or diag(A) with the Jacobi option)
 //   CG_LIST   list form only: compact the free mask into an index list
