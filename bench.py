@@ -420,6 +420,8 @@ def main():
                     help="CG stopping test: relative decrease (the paper's) or residual")
     ap.add_argument("--tile", type=int, default=0,
                     help="unknowns per tile (multiple of 256; 0 = library choice)")
+    ap.add_argument("--cg-kernel", default="auto", choices=["auto", "on", "off"],
+                    help="split form: CG iterations in a data kernel of their own")
     ap.add_argument("--lookahead", default="auto", choices=["auto", "on", "off"],
                     help="fused form: trial passes also evaluate the next step length")
     ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
@@ -483,8 +485,10 @@ def main():
     cs = gpcg.GPCG_CGSTOP_RESIDUAL if args.cg_stop == "residual" else gpcg.GPCG_CGSTOP_DECREASE
     la = {"auto": gpcg.GPCG_LOOKAHEAD_AUTO, "on": gpcg.GPCG_LOOKAHEAD_ON,
           "off": gpcg.GPCG_LOOKAHEAD_OFF}[args.lookahead]
+    ck = {"auto": gpcg.GPCG_CGK_AUTO, "on": gpcg.GPCG_CGK_ON,
+          "off": gpcg.GPCG_CGK_OFF}[args.cg_kernel]
     solver = gpcg.Solver(op, device=dev, form=form, free_set=fs, prefetch=pf, precond=pc,
-                         cg_stop=cs, lookahead=la, tiles_per_wg=args.tiles_per_wg,
+                         cg_stop=cs, lookahead=la, cg_kernel=ck, tiles_per_wg=args.tiles_per_wg,
                          chunk=args.chunk, tile=args.tile, **opts)
     b, l, u, x0 = t(inst.b), t(inst.l), t(inst.u), t(inst.x0)
     x = torch.empty_like(x0)
@@ -495,7 +499,7 @@ def main():
 
     tuned = None
     if (not args.no_autotune and args.form == "auto" and args.tiles_per_wg == 0
-            and args.prefetch == "auto" and args.chunk == 0):
+            and args.prefetch == "auto" and args.chunk == 0 and args.cg_kernel == "auto"):
         tuned = solver.autotune(b, l, u, x0)["chosen"]
         log(f"autotune: {tuned}")
     for _ in range(args.warmup):
@@ -558,7 +562,8 @@ def main():
                    "free_set": args.free_set, "form": args.form,
                    "tiles_per_wg": args.tiles_per_wg, "prefetch": args.prefetch,
                    "precond": args.precond, "cg_stop": args.cg_stop,
-                   "lookahead": args.lookahead, "chunk": args.chunk, "tile": args.tile,
+                   "lookahead": args.lookahead, "cg_kernel": args.cg_kernel,
+                   "chunk": args.chunk, "tile": args.tile,
                    "grid": f"{N}x{N}", "tol_rel": 1e-8, "global_batch": 1,
                    "parallelism": "single GPU"},
         "roofline": {

@@ -134,6 +134,13 @@ typedef struct {
                           stencil has a constant diagonal, which leaves the
                           iterates unchanged: there it is not applied      */
   int32_t cg_stop;      /* GPCG_CGSTOP_DECREASE (default) or _RESIDUAL       */
+  int32_t cg_kernel;    /* split form: GPCG_CGK_ON runs the CG iterations of
+                          stencil QPs (mask free set) in a data kernel of
+                          their own, which needs far fewer registers than the
+                          kernel of every pass and so keeps more workgroups
+                          in flight, at the price of a third launch per pass;
+                          GPCG_CGK_OFF one data kernel; GPCG_CGK_AUTO the
+                          library's choice.  The answer does not depend on it */
   int32_t lookahead;    /* fused form, stencil operators, 256-unknown tiles:
                           the pass that evaluates a trial point of the
                           gradient-projection search also evaluates eq.
@@ -150,6 +157,10 @@ typedef struct {
 #define GPCG_CGSTOP_RESIDUAL 1 /* ||r_k + A_k w_j|| <= eta_2 ||r_k||, the standard
                                   test the paper contrasts with eq. (cgstop1)
                                   (M^-1 norm when preconditioned)               */
+
+#define GPCG_CGK_AUTO 0
+#define GPCG_CGK_ON 1
+#define GPCG_CGK_OFF 2
 
 #define GPCG_LOOKAHEAD_AUTO 0
 #define GPCG_LOOKAHEAD_ON 1
@@ -170,7 +181,7 @@ typedef struct {
  * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
  * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO,
  * precond GPCG_PRECOND_NONE, cg_stop GPCG_CGSTOP_DECREASE,
- * lookahead GPCG_LOOKAHEAD_AUTO. */
+ * cg_kernel GPCG_CGK_AUTO, lookahead GPCG_LOOKAHEAD_AUTO. */
 void gpcg_options_default(gpcg_options *opt);
 
 /* ------------------------------------------------------------------- stats */
@@ -267,7 +278,8 @@ typedef struct {
   int32_t chunk;        /* passes per graph replay                           */
   int32_t shrink;       /* stepped batch: the launch is re-formed over the
                            unfinished QPs once 1/shrink of its tiles are done */
-  int32_t pad;
+  int32_t cg_kernel;    /* split form, 1: CG iterations in a data kernel of
+                           their own (see gpcg_options.cg_kernel)            */
   double ms;            /* wall time of one solve                            */
 } gpcg_tune_entry;
 

@@ -41,6 +41,7 @@ GPCG_PREFETCH_AUTO, GPCG_PREFETCH_ON, GPCG_PREFETCH_OFF = 0, 1, 2
 GPCG_PRECOND_NONE, GPCG_PRECOND_JACOBI = 0, 1
 GPCG_CGSTOP_DECREASE, GPCG_CGSTOP_RESIDUAL = 0, 1
 GPCG_LOOKAHEAD_AUTO, GPCG_LOOKAHEAD_ON, GPCG_LOOKAHEAD_OFF = 0, 1, 2
+GPCG_CGK_AUTO, GPCG_CGK_ON, GPCG_CGK_OFF = 0, 1, 2
 
 
 class gpcg_operator(C.Structure):
@@ -57,7 +58,8 @@ class gpcg_options(C.Structure):
                 ("tile", C.c_int32), ("chunk", C.c_int32), ("use_graph", C.c_int32),
                 ("max_stall", C.c_int32), ("form", C.c_int32),
                 ("tiles_per_wg", C.c_int32), ("prefetch", C.c_int32),
-                ("precond", C.c_int32), ("cg_stop", C.c_int32), ("lookahead", C.c_int32)]
+                ("precond", C.c_int32), ("cg_stop", C.c_int32), ("cg_kernel", C.c_int32),
+                ("lookahead", C.c_int32)]
 
 
 class gpcg_stats(C.Structure):
@@ -101,7 +103,7 @@ GPCG_TUNE_MAX = 32
 
 class gpcg_tune_entry(C.Structure):
     _fields_ = [("form", C.c_int32), ("tiles_per_wg", C.c_int32), ("prefetch", C.c_int32),
-                ("chunk", C.c_int32), ("shrink", C.c_int32), ("pad", C.c_int32),
+                ("chunk", C.c_int32), ("shrink", C.c_int32), ("cg_kernel", C.c_int32),
                 ("ms", C.c_double)]
 
     def as_dict(self):

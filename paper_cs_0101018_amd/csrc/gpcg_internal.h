@@ -146,18 +146,24 @@ struct PersistLaunch {
 // Kernel variants (the `spec` argument of the launchers below is a set of
 // these bits).  kVarSpec: the launch holds only stencil QPs with 256-unknown
 // tiles, which may load CG operands before the state is known.  kVarPre: some
-// QP of the launch has the Jacobi preconditioner.
+// QP of the launch has the Jacobi preconditioner.  kVarCgk: split form, the
+// lean CG iterations run in a data kernel of their own (fewer registers, more
+// workgroups in flight) and the data kernel of the other passes skips them.
 constexpr int kVarSpec = 1;
 constexpr int kVarPre = 2;
+constexpr int kVarCgk = 4;
 
 }  // namespace gpcg
 
 extern "C++" {
 void *gpcg_step_kernel_ptr(int mixed, int spec);
 int gpcg_launch_step(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
-// Split form: a transition kernel (grid = QPs) then a data kernel (grid = tiles).
+// Split form: a transition kernel (grid = QPs) then a data kernel (grid = tiles);
+// with kVarCgk two data kernels, the CG kernel (gpcg_pass_kernel_ptr) and the
+// kernel of the other passes (gpcg_rest_kernel_ptr), on the same grid.
 void *gpcg_transition_kernel_ptr();
 void *gpcg_pass_kernel_ptr(int mixed, int spec);
+void *gpcg_rest_kernel_ptr(int mixed, int spec);
 int gpcg_launch_split(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
 int gpcg_launch_spmv(const gpcg::QPDev *dqp, int64_t n, const void *v, void *y,
                      const uint8_t *mask, int f32, int vec_nx, void *stream);

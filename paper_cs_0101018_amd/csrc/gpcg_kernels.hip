@@ -1386,8 +1386,12 @@ static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 // iterations of stencil QPs in the mask form take the lean path (operands of
 // the tile, neighbours exchanged through LDS); with SPEC its loads for the
 // first tile are issued before the state is read, which costs registers in
-// every phase.
-template <typename CT, bool SPEC, bool PRE>
+// every phase.  PART: kPartAll runs every pass; kPartCG only the lean CG
+// iterations (the lean path alone needs far fewer registers, so more
+// workgroups stay in flight); kPartRest every pass but those.
+constexpr int kPartAll = 0, kPartCG = 1, kPartRest = 2;
+
+template <typename CT, bool SPEC, bool PRE, int PART = kPartAll>
 __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
   __shared__ QPStatic ss;
@@ -1421,7 +1425,10 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   double *slots = tile_slots(q);
   const int t1 = t0 + nt < ntiles ? t0 + nt : ntiles;
   const bool lean = SPEC || (S->op_kind != OPK_CSR && S->list == nullptr);
-  if (phase == PH_CG_ITER && lean) {
+  const bool lean_cg = phase == PH_CG_ITER && lean;
+  if (PART == kPartCG && !lean_cg) return;
+  if (PART == kPartRest && lean_cg) return;
+  if (PART != kPartRest && lean_cg) {
     // a tile of several 256-unknown chunks accumulates them in order, as
     // run_pass does (thread t: unknowns k0 + t, k0 + t + 256, ...)
     const int nchunk = S->tile / kBlock;
@@ -1448,6 +1455,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     }
     return;
   }
+  if constexpr (PART == kPartCG) return;
   for (int tile = t0; tile < t1; ++tile) {
     const int64_t k0 = (int64_t)tile * S->tile;
     const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
@@ -1723,14 +1731,32 @@ int gpcg_launch_persistent(const PersistLaunch &P, int grid, int mixed, void *st
 
 void *gpcg_transition_kernel_ptr() { return (void *)&transition_kernel; }
 
-void *gpcg_pass_kernel_ptr(int mixed, int variant) {
+template <int PART>
+static void *pass_ptr(int mixed, int variant) {
   const bool sp = variant & kVarSpec, pr = variant & kVarPre;
   if (mixed) {
-    if (sp) return pr ? (void *)&pass_kernel<float, true, true> : (void *)&pass_kernel<float, true, false>;
-    return pr ? (void *)&pass_kernel<float, false, true> : (void *)&pass_kernel<float, false, false>;
+    if (sp)
+      return pr ? (void *)&pass_kernel<float, true, true, PART>
+                : (void *)&pass_kernel<float, true, false, PART>;
+    return pr ? (void *)&pass_kernel<float, false, true, PART>
+              : (void *)&pass_kernel<float, false, false, PART>;
   }
-  if (sp) return pr ? (void *)&pass_kernel<double, true, true> : (void *)&pass_kernel<double, true, false>;
-  return pr ? (void *)&pass_kernel<double, false, true> : (void *)&pass_kernel<double, false, false>;
+  if (sp)
+    return pr ? (void *)&pass_kernel<double, true, true, PART>
+              : (void *)&pass_kernel<double, true, false, PART>;
+  return pr ? (void *)&pass_kernel<double, false, true, PART>
+            : (void *)&pass_kernel<double, false, false, PART>;
+}
+
+void *gpcg_pass_kernel_ptr(int mixed, int variant) {
+  return (variant & kVarCgk) ? pass_ptr<kPartCG>(mixed, variant)
+                             : pass_ptr<kPartAll>(mixed, variant);
+}
+
+// The kernel of the passes the CG kernel skips: the early CG loads are of no
+// use there.
+void *gpcg_rest_kernel_ptr(int mixed, int variant) {
+  return pass_ptr<kPartRest>(mixed, variant & kVarPre);
 }
 
 int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
@@ -1739,6 +1765,9 @@ int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
   hipLaunchKernelGGL(transition_kernel, dim3(tgrid), dim3(kBlock), 0, (hipStream_t)stream, L);
   hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_pass_kernel_ptr(mixed, spec)),
                      dim3(L.data_grid), dim3(kBlock), 0, (hipStream_t)stream, L);
+  if (spec & kVarCgk)
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_rest_kernel_ptr(mixed, spec)),
+                       dim3(L.data_grid), dim3(kBlock), 0, (hipStream_t)stream, L);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

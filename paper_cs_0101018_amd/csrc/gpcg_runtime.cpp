@@ -111,6 +111,8 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "unknown CG stopping test");
   if (o->lookahead < GPCG_LOOKAHEAD_AUTO || o->lookahead > GPCG_LOOKAHEAD_OFF)
     return fail(GPCG_ERR_ARG, "unknown lookahead mode");
+  if (o->cg_kernel < GPCG_CGK_AUTO || o->cg_kernel > GPCG_CGK_OFF)
+    return fail(GPCG_ERR_ARG, "unknown cg_kernel mode");
   return GPCG_OK;
 }
 
@@ -339,6 +341,8 @@ int build_chain_graph(const StepLaunch &L, int mixed, int spec, int split, int c
     if (split) {
       rc = add(gpcg_transition_kernel_ptr(), L.single ? 1u : (unsigned)L.nqp, arg);
       if (!rc) rc = add(gpcg_pass_kernel_ptr(mixed, spec), (unsigned)L.data_grid, arg);
+      if (!rc && (spec & kVarCgk))
+        rc = add(gpcg_rest_kernel_ptr(mixed, spec), (unsigned)L.data_grid, arg);
     } else {
       rc = add(gpcg_step_kernel_ptr(mixed, spec), (unsigned)L.total_tiles, arg);
     }
@@ -451,9 +455,10 @@ struct LaunchCfg {
   int spec;          // CG operands loaded before the state is known (stencils)
   int chunk;         // passes per graph replay / host check (even)
   int shrink = 3;    // stepped batch: re-form the launch once 1/shrink of its tiles are done
+  int cgk = 0;       // split form: CG iterations in a data kernel of their own
   bool operator==(const LaunchCfg &o) const {
     return split == o.split && tiles_per_wg == o.tiles_per_wg && spec == o.spec &&
-           chunk == o.chunk && shrink == o.shrink;
+           chunk == o.chunk && shrink == o.shrink && cgk == o.cgk;
   }
   bool operator!=(const LaunchCfg &o) const { return !(*this == o); }
 };
@@ -614,6 +619,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->precond = GPCG_PRECOND_NONE;
   o->cg_stop = GPCG_CGSTOP_DECREASE;
   o->lookahead = GPCG_LOOKAHEAD_AUTO;
+  o->cg_kernel = GPCG_CGK_AUTO;
 }
 
 int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_t *bytes) {
@@ -670,8 +676,9 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   h->cfg.tiles_per_wg = o.tiles_per_wg > 0 ? o.tiles_per_wg : 1;
   h->cfg.spec = spec_ok(h->st) && o.prefetch != GPCG_PREFETCH_OFF ? 1 : 0;
   h->cfg.chunk = default_chunk(o);
+  h->cfg.cgk = o.cg_kernel == GPCG_CGK_ON ? 1 : 0;
   if (o.form == GPCG_FORM_AUTO && o.tiles_per_wg == 0 && o.chunk == 0 &&
-      o.prefetch == GPCG_PREFETCH_AUTO) {
+      o.prefetch == GPCG_PREFETCH_AUTO && o.cg_kernel == GPCG_CGK_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(h));
     if (it != g_tuned.end()) h->cfg = it->second;
@@ -732,7 +739,8 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   SL.nqp = 1;
   SL.total_tiles = h->L.ntiles;
   const LaunchCfg c = h->cfg;
-  const int variant = (c.spec ? kVarSpec : 0) | (h->st.dinv ? kVarPre : 0);
+  const int variant = (c.spec ? kVarSpec : 0) | (h->st.dinv ? kVarPre : 0) |
+                      (c.split && c.cgk ? kVarCgk : 0);
   SL.tiles_per_wg = c.tiles_per_wg;
   SL.data_grid = (h->L.ntiles + c.tiles_per_wg - 1) / c.tiles_per_wg;
   const int chunk = c.chunk;
@@ -798,6 +806,7 @@ void note(gpcg_tune_report *r, const LaunchCfg &c, double ms) {
   e.prefetch = c.spec;
   e.chunk = c.chunk;
   e.shrink = c.shrink;
+  e.cg_kernel = c.cgk;
   e.ms = ms;
 }
 
@@ -849,6 +858,11 @@ int gpcg_autotune(gpcg_handle h, const double *b, const double *l, const double 
         c.tiles_per_wg = t;
         if ((rc = consider(c)) < 0) return rc;
       }
+  if (best.split) {
+    LaunchCfg c = best;
+    c.cgk = best.cgk ? 0 : 1;
+    if ((rc = consider(c)) < 0) return rc;
+  }
   if (spec_ok(h->st)) {
     LaunchCfg c = best;
     c.spec = best.spec ? 0 : 1;
@@ -1069,6 +1083,7 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->tbytes = need;
   b->mixed = handles[0]->st.mixed;
   b->cfg = LaunchCfg{1, 1, 1, default_chunk(handles[0]->opt), 3};
+  b->cfg.cgk = handles[0]->opt.cg_kernel == GPCG_CGK_ON ? 1 : 0;
   int rc = alloc_flag(&b->flags, (size_t)count);
   if (rc) {
     delete b;
@@ -1174,7 +1189,7 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
         sp = sp && spec_ok(b->hs[i]->st);
         pre = pre || b->hs[i]->st.dinv != nullptr;
       }
-      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0);
+      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0);
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
       if (rc) return rc;
@@ -1275,6 +1290,11 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
   }
   {
     LaunchCfg c = best;
+    c.cgk = best.cgk ? 0 : 1;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  {
+    LaunchCfg c = best;
     c.spec = best.spec ? 0 : 1;
     if ((rc = consider(c)) < 0) return rc;
   }
@@ -1296,6 +1316,7 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     report->chosen.prefetch = best.spec;
     report->chosen.chunk = best.chunk;
     report->chosen.shrink = best.shrink;
+    report->chosen.cg_kernel = best.cgk;
     report->chosen.ms = best_ms;
   }
   if (mismatches) return fail(GPCG_ERR_HIP, "batch autotune: launch configurations disagreed");

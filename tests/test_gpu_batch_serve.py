@@ -52,13 +52,18 @@ def test_batch_equals_alone(mode, mixed):
         assert st["passes"] == sa["passes"] + sa["lookaheads"], inst.name
 
 
+@pytest.mark.parametrize("cgk", [0, 1], ids=["one_data_kernel", "cg_kernel"])
 @pytest.mark.parametrize("mixed", [0, 1])
-def test_batch_equals_alone_many_tiles(mixed):
+def test_batch_equals_alone_many_tiles(mixed, cgk):
     """Members with more tiles than threads per workgroup (their slot sums
-    have tails): the batch (split form) equals each one alone (fused form)."""
+    have tails): the batch (split form) equals each one alone (fused form),
+    with the CG iterations in the data kernel of every pass or in one of
+    their own."""
+    import paper_cs_0101018_amd as gpcg
     insts = [instances.obstacle(300, 4, amplitude=0.4), instances.varcoef(270, 1),
              instances.obstacle(45, 2), instances.obstacle(560, 3)]  # 560^2: 512-unknown tiles
-    xs, stats = _batch(insts, 0, precision=mixed)
+    ck = gpcg.GPCG_CGK_ON if cgk else gpcg.GPCG_CGK_OFF
+    xs, stats = _batch(insts, 0, precision=mixed, cg_kernel=ck)
     for inst, x, st in zip(insts, xs, stats):
         xa, ga, sa = solo(inst, precision=mixed)
         assert st["status"] == sa["status"] == 0, (st, sa)

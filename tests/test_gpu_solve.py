@@ -170,6 +170,11 @@ def test_fused_and_split_forms_agree_bitwise(case):
     res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT,
                        use_graph=0, chunk=10))
     res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT, tiles_per_wg=3))
+    # the CG iterations in a data kernel of their own
+    res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT,
+                       cg_kernel=gpcg.GPCG_CGK_ON))
+    res.append(G.solve(inst, kind, precision=prec, form=gpcg.GPCG_FORM_SPLIT, tiles_per_wg=2,
+                       cg_kernel=gpcg.GPCG_CGK_ON, prefetch=gpcg.GPCG_PREFETCH_OFF))
     (x1, g1, s1) = res[0]
     assert s1["status"] == gpcg.GPCG_OK
     for x, g, st in res[1:]:
