@@ -530,19 +530,25 @@ def main():
     if tuned is not None:
         fused = tuned["form"] == gpcg.GPCG_FORM_FUSED
         prefetch = bool(tuned["prefetch"])
+        cgk = bool(tuned["cg_kernel"]) and not fused
     else:
         fused = args.form == "fused" or (args.form == "auto" and ntiles <= 1024)
-        prefetch = args.prefetch != "off"
+        # early CG loads need 256-unknown tiles (the library's choice up to
+        # 1024 of them) and the mask free set
+        tile = args.tile or (256 if ntiles <= 1024 else 512)
+        prefetch = args.prefetch != "off" and tile == 256 and args.free_set == "mask"
+        cgk = args.cg_kernel == "on" and not fused
     ct = "float" if opts.get("precision") else "double"
-    variant = (f"<{ct}, {'true' if prefetch else 'false'}, "
-               f"{'true' if args.precond == 'jacobi' else 'false'}>")
+    flags = (f"{ct}, {'true' if prefetch else 'false'}, "
+             f"{'true' if args.precond == 'jacobi' else 'false'}")
     if fused:
-        kname = f"gpcg::step_kernel{variant} (one fused GPCG pass per launch)"
-        ksub = f"step_kernel{variant}"
+        kname = f"gpcg::step_kernel<{flags}> (one fused GPCG pass per launch)"
+        ksub = f"step_kernel<{flags}>"
     else:
-        kname = (f"gpcg::pass_kernel{variant} (data kernel of the split form; the time per "
-                 "launch is that of one transition + data kernel pair)")
-        ksub = f"pass_kernel{variant}"
+        part = 1 if cgk else 0  # the CG iterations' own data kernel, or the one of every pass
+        kname = (f"gpcg::pass_kernel<{flags}, {part}> (data kernel of the split form; the time "
+                 "per launch is that of one pass: transition and data kernels)")
+        ksub = f"pass_kernel<{flags}, {part}>"
     traffic = traffic_from_profile(args.workload, ksub)
 
     res = {

@@ -144,7 +144,9 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free
   const int64_t n = op_n(op);
   const bool mixed = precision == GPCG_PREC_MIXED;
   const size_t ct = mixed ? 4 : 8;
-  L.tile = tile_opt > 0 ? tile_opt : tuned_tile(n);
+  // the list form compacts the free set tile by tile with one unknown per
+  // thread: it keeps 256-unknown tiles at every size
+  L.tile = tile_opt > 0 ? tile_opt : (free_set == GPCG_FREESET_LIST ? kBlock : tuned_tile(n));
   L.ntiles = (int)((n + L.tile - 1) / L.tile);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -884,6 +886,7 @@ int gpcg_autotune(gpcg_handle h, const double *b, const double *l, const double 
     report->chosen.tiles_per_wg = best.tiles_per_wg;
     report->chosen.prefetch = best.spec;
     report->chosen.chunk = best.chunk;
+    report->chosen.cg_kernel = best.cgk;
     report->chosen.ms = best_ms;
   }
   if (mismatches) return fail(GPCG_ERR_HIP, "autotune: launch configurations disagreed");

@@ -105,3 +105,21 @@ def test_list_form_in_a_batch_matches_alone():
     b.close()
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_list_form_large_grid(prec):
+    """Beyond 262,144 unknowns the mask form uses 512-unknown tiles; the list
+    form keeps 256 (its compaction works one unknown per thread).  Its answer
+    meets the parity bar against the mask form's, and both launch forms agree
+    bitwise."""
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.obstacle(530, 6, amplitude=0.4)
+    tol, bar = (TIGHT, 1e-8) if prec == 0 else (1e-10, 1e-6)
+    xm, gm, sm = G.solve(inst, precision=0, tol_rel=TIGHT)
+    outs = [G.solve(inst, precision=prec, tol_rel=tol, free_set=gpcg.GPCG_FREESET_LIST, form=f)
+            for f in (gpcg.GPCG_FORM_FUSED, gpcg.GPCG_FORM_SPLIT)]
+    for x, g, st in outs:
+        assert st["status"] == gpcg.GPCG_OK, st
+        assert G.rel_inf(x, xm) <= bar
+    assert np.array_equal(outs[0][0], outs[1][0])
