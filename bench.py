@@ -47,6 +47,10 @@ WORKLOADS = {
     "obstacle1600_mixed": ("obstacle_ub_1600", dict(precision=1), "GPCG mixed, obstacle 1600x1600"),
     "bearing256_fp64": ("bearing256", dict(), "GPCG FP64, -div(c grad u) 256x256, "
                         "c=(1+0.9 cos 2 pi s)^3 (eccentricity 0.9), l=0, u=inf, tol 1e-8 rel"),
+    # small free set, CSR operator (the matrix free set's case)
+    "pressed512_csr_fp64": ("pressed512", dict(operator="csr"),
+                            "GPCG FP64, obstacle 512x512 pressed onto its obstacle (b=-1e4), "
+                            "CSR operator, 23% free at the solution"),
 }
 BATCH_WORKLOADS = ("batch512_fp64", "batch512_mixed")
 SERVE_WORKLOADS = ("serve4096",)
@@ -156,6 +160,8 @@ def make_instance(key):
         return instances.varcoef(256, 0, eps=0.9, name="bearing256")
     if key.startswith("obstacle_ub_"):
         return instances.obstacle_ub(int(key.split("_")[-1]), 0)
+    if key == "pressed512":
+        return instances.pressed(512, 0)
     raise KeyError(key)
 
 
@@ -249,6 +255,8 @@ def bench_batch(args, gpcg, torch, dev):
     insts = instances.batch512(0)
     data = [_dev_instance(i, gpcg, torch, dev) for i in insts]
     mode = gpcg.GPCG_BATCH_PERSISTENT if args.batch_mode == "persistent" else gpcg.GPCG_BATCH_STEPPED
+    if args.free_set == "matrix":
+        sys.exit("the matrix free set needs CSR operators; the batch members are stencils")
     fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
     pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
     solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed), free_set=fs, precond=pc)
@@ -424,8 +432,9 @@ def main():
                     help="split form: CG iterations in a data kernel of their own")
     ap.add_argument("--lookahead", default="auto", choices=["auto", "on", "off"],
                     help="fused form: trial passes also evaluate the next step length")
-    ap.add_argument("--free-set", default="mask", choices=["mask", "list"],
-                    help="free set of the reduced CG: byte mask or compacted list")
+    ap.add_argument("--free-set", default="mask", choices=["mask", "list", "matrix"],
+                    help="free set of the reduced CG: byte mask, compacted list, or the "
+                         "list with the reduced matrix written out (CSR operators)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (run during warmup, untimed)")
@@ -471,14 +480,22 @@ def main():
         log("copy-calib: 268435456 bytes read + written")
         del a, b
 
-    if inst.op == "var":
+    opts = dict(opts)
+    csr = opts.pop("operator", None) == "csr"
+    if args.free_set == "matrix" and not csr:
+        sys.exit("the matrix free set needs a CSR operator (e.g. --workload pressed512_csr_fp64)")
+    if csr:
+        rowptr, colind, vals = inst.csr()
+        op = gpcg.Operator.csr(t(rowptr), t(colind), t(vals))
+    elif inst.op == "var":
         wx, wy = inst.edge_weights()
         op = gpcg.Operator.stencil_var(N, N, t(wx.ravel()), t(wy.ravel()))
     else:
         op = gpcg.Operator.stencil_const(N, N, inst.w)
     form = {"auto": gpcg.GPCG_FORM_AUTO, "fused": gpcg.GPCG_FORM_FUSED,
             "split": gpcg.GPCG_FORM_SPLIT}[args.form]
-    fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
+    fs = {"mask": gpcg.GPCG_FREESET_MASK, "list": gpcg.GPCG_FREESET_LIST,
+          "matrix": gpcg.GPCG_FREESET_MATRIX}[args.free_set]
     pf = {"auto": gpcg.GPCG_PREFETCH_AUTO, "on": gpcg.GPCG_PREFETCH_ON,
           "off": gpcg.GPCG_PREFETCH_OFF}[args.prefetch]
     pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
@@ -536,19 +553,24 @@ def main():
         # early CG loads need 256-unknown tiles (the library's choice up to
         # 1024 of them) and the mask free set
         tile = args.tile or (256 if ntiles <= 1024 else 512)
-        prefetch = args.prefetch != "off" and tile == 256 and args.free_set == "mask"
+        prefetch = (args.prefetch != "off" and tile == 256 and args.free_set == "mask"
+                    and not csr)
         cgk = args.cg_kernel == "on" and not fused
     ct = "float" if opts.get("precision") else "double"
+    mat = "true" if args.free_set == "matrix" else "false"
     flags = (f"{ct}, {'true' if prefetch else 'false'}, "
              f"{'true' if args.precond == 'jacobi' else 'false'}")
     if fused:
-        kname = f"gpcg::step_kernel<{flags}> (one fused GPCG pass per launch)"
-        ksub = f"step_kernel<{flags}>"
+        kname = f"gpcg::step_kernel<{flags}, {mat}> (one fused GPCG pass per launch)"
+        ksub = f"step_kernel<{flags}, {mat}>"
     else:
-        part = 1 if cgk else 0  # the CG iterations' own data kernel, or the one of every pass
-        kname = (f"gpcg::pass_kernel<{flags}, {part}> (data kernel of the split form; the time "
-                 "per launch is that of one pass: transition and data kernels)")
-        ksub = f"pass_kernel<{flags}, {part}>"
+        # the CG iterations' own data kernel, or the one of every pass; the
+        # matrix form never runs in the CG-only kernel
+        part = 1 if cgk and mat == "false" else 0
+        pmat = "false" if part == 1 else mat
+        kname = (f"gpcg::pass_kernel<{flags}, {part}, {pmat}> (data kernel of the split form; "
+                 "the time per launch is that of one pass: transition and data kernels)")
+        ksub = f"pass_kernel<{flags}, {part}, {pmat}>"
     traffic = traffic_from_profile(args.workload, ksub)
 
     res = {

@@ -90,6 +90,10 @@ typedef struct {
 
 #define GPCG_FREESET_MASK 0 /* CG vectors full length, zero on the active set */
 #define GPCG_FREESET_LIST 1 /* CG loops over a compacted list of free indices */
+#define GPCG_FREESET_MATRIX 2 /* CSR operators: the list form plus the reduced
+                               matrix A_F (rows and columns of the free set;
+                               the paper's technique 1) written out once per
+                               CG phase; CG iterations read only its nonzeros */
 
 typedef struct {
   double tol_rel;      /* stop when ||P grad q(x)||_2 <= tau,                 */

@@ -162,8 +162,8 @@ def _obstacle_lower(N, rng, amplitude=0.3):
 
 
 def obstacle(N: int, seed: int = 0, *, amplitude: float = 0.3, u_random: bool = False,
-             name: Optional[str] = None) -> Instance:
-    """Obstacle-type QP: constant 5-point Laplacian / h^2, b = 1.
+             load: float = 1.0, name: Optional[str] = None) -> Instance:
+    """Obstacle-type QP: constant 5-point Laplacian / h^2, b = load (1 by default).
 
     Draws, in order: z ~ N(0,1) for l (n values); then, if ``u_random``,
     w ~ U(0,1) for u = 0.25 + 0.05 w (n values).  Otherwise u = 0.25.
@@ -180,9 +180,16 @@ def obstacle(N: int, seed: int = 0, *, amplitude: float = 0.3, u_random: bool = 
         u = np.full(n, 0.25)
     u = np.maximum(u, l)
     x0 = np.minimum(np.maximum(l, 0.0), u)
-    return Instance(name or f"obstacle{N}", N, OP_CONST, b=np.ones(n), l=l, u=u, x0=x0,
-                    w=1.0 / h**2, meta=dict(seed=seed, amplitude=amplitude,
-                                            u_random=u_random))
+    return Instance(name or f"obstacle{N}", N, OP_CONST, b=np.full(n, float(load)), l=l, u=u,
+                    x0=x0, w=1.0 / h**2, meta=dict(seed=seed, amplitude=amplitude,
+                                                   u_random=u_random, load=load))
+
+
+def pressed(N: int, seed: int = 0, load: float = -10000.0) -> Instance:
+    """An obstacle QP pressed onto its obstacle (b = load < 0, amplitude 0.3),
+    the case of a small free set: at the solution 23 % of the unknowns are
+    free for N = 512 and the default load, 25 % for N = 256 and load -2500."""
+    return obstacle(N, seed, amplitude=0.3, load=load, name=f"pressed{N}")
 
 
 def varcoef(N: int, seed: int = 0, *, eps: float = 0.1, name: Optional[str] = None) -> Instance:

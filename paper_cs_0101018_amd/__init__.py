@@ -34,7 +34,7 @@ GPCG_ERR_ARG, GPCG_ERR_BOUNDS, GPCG_ERR_NAN, GPCG_ERR_NOT_SPD = -1, -2, -3, -4
 GPCG_ERR_WORKSPACE, GPCG_ERR_HIP, GPCG_ERR_NOSPACE, GPCG_ERR_HANG = -5, -6, -7, -8
 GPCG_OP_STENCIL5_CONST, GPCG_OP_STENCIL5_VAR, GPCG_OP_CSR = 1, 2, 3
 GPCG_PREC_FP64, GPCG_PREC_MIXED = 0, 1
-GPCG_FREESET_MASK, GPCG_FREESET_LIST = 0, 1
+GPCG_FREESET_MASK, GPCG_FREESET_LIST, GPCG_FREESET_MATRIX = 0, 1, 2
 GPCG_BATCH_STEPPED, GPCG_BATCH_PERSISTENT = 0, 1
 GPCG_FORM_AUTO, GPCG_FORM_FUSED, GPCG_FORM_SPLIT = 0, 1, 2
 GPCG_PREFETCH_AUTO, GPCG_PREFETCH_ON, GPCG_PREFETCH_OFF = 0, 1, 2

@@ -29,6 +29,8 @@ enum Phase : int32_t {
   PH_CG_ITER,     // one single-reduction CG iteration on the free set
   PH_PS_TRIAL,    // x' = P[x + alpha w] and g' = Ax' - b: decrease and face of x'
   PH_CG_LIST,     // list form: compact the free mask into an ascending index list
+  PH_CG_MCOUNT,   // matrix form: free columns of every free row (nonzeros of A_F)
+  PH_CG_MFILL,    // matrix form: write A_F (rows of the list, free columns only)
   PH_DONE,
   PH_COUNT
 };
@@ -61,6 +63,8 @@ struct QPStatic {
   void *pv, *wv;                 // CG direction and iterate
   uint8_t *mask;                 // free set of the current CG phase
   int32_t *list;                 // list form: free indices in ascending order (else null)
+  int32_t *mrow, *mcol;          // matrix form: A_F as CSR over the list (row pointers,
+  void *mval;                    //   grid column indices, values FP64/FP32), or null
   const void *dinv;              // Jacobi preconditioner: 1 / diag(A) (FP64/FP32), or null
   int32_t *host_flag;            // device view of a mapped host word, or null
   double tol_rel, tol_abs, eta1, eta2, eta2_reduce, mu;
@@ -79,6 +83,7 @@ struct QPCore {
   int64_t m_free, n_lower, n_upper, n_nonbinding;
   int64_t passes, cg_free_rows;
   int64_t lookaheads;  // eq. (bqpls) evaluated inside a trial pass
+  int64_t nnz_free, cg_free_nnz;  // matrix form: nonzeros of A_F; summed over CG passes
 };
 
 // One copy of the state per launch parity: the core plus per-pass counters.
@@ -152,6 +157,9 @@ struct PersistLaunch {
 constexpr int kVarSpec = 1;
 constexpr int kVarPre = 2;
 constexpr int kVarCgk = 4;
+// kVarMat: some QP of the launch has the matrix free set (the kernels that
+// carry its count and fill passes; never with kVarSpec).
+constexpr int kVarMat = 8;
 
 }  // namespace gpcg
 

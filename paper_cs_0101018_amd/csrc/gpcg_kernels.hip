@@ -266,7 +266,7 @@ __device__ __forceinline__ int nslots(int phase) {
   switch (phase) {
     case PH_GP_ALPHA: case PH_CG_ITER: return 2;
     case PH_CG_INIT: return 3;
-    case PH_CG_LIST: return 1;
+    case PH_CG_LIST: case PH_CG_MCOUNT: case PH_CG_MFILL: return 1;
     default: return kNP;
   }
 }
@@ -357,6 +357,72 @@ __device__ __forceinline__ void sum_partials(const double *slots, int par, int n
 }
 
 // ------------------------------------------------------------ the passes
+
+// Exclusive prefix sum of v over the workgroup in thread order (valid in every
+// thread); total receives the sum.  Every thread must call it.
+__device__ __forceinline__ int block_exscan(int v, int &total) {
+  __shared__ int s_w[kBlock / 64];
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wv] = x;
+  __syncthreads();
+  int off = 0;
+  for (int i = 0; i < wv; ++i) off += s_w[i];
+  total = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+  __syncthreads();  // s_w is reused by the next call
+  return off + x - v;
+}
+
+// Free columns of row k of a CSR operator.
+__device__ __forceinline__ int free_cols(const QPStatic *S, int64_t k) {
+  int c = 0;
+  for (int32_t p = S->rowptr[k]; p < S->rowptr[k + 1]; ++p) c += S->mask[S->colind[p]] ? 1 : 0;
+  return c;
+}
+
+// Matrix form, fill pass: A_F (the reduced matrix of the paper's technique 1)
+// as CSR over the list, columns as grid indices, one list entry per thread
+// (entries [k0, k1) of the list).  The offset of this tile's rows is the
+// number of nonzeros of the list tiles before it (slot 0 of the count pass).
+template <typename CT>
+__device__ __forceinline__ void matrix_fill(const QPStatic *__restrict__ S,
+                                         const double *__restrict__ slots, int64_t m_free,
+                                         int lpar, int64_t k0, int64_t k1) {
+  const int tile = (int)(k0 / kBlock);
+  double before[1] = {0.0};
+  for (int t = (int)threadIdx.x; t < tile; t += kBlock)
+    before[0] += slots[slot_index(t, lpar, 0)];
+  block_sum<double, 1>(before);
+  __shared__ int64_t s_mbase;
+  if (threadIdx.x == 0) s_mbase = (int64_t)before[0];
+  const int64_t e1 = k1 < m_free ? k1 : m_free;
+  const int64_t e = k0 + threadIdx.x;
+  const bool row = e < e1;
+  const int64_t k = row ? S->list[e] : 0;
+  const int c = row ? free_cols(S, k) : 0;
+  int total;
+  const int pos = block_exscan(c, total);
+  if (row) {
+    const OpView<CT> A = op_view<CT>(S);
+    CT *__restrict__ mv = (CT *)S->mval;
+    int64_t at = s_mbase + pos;
+    if (e == 0) S->mrow[0] = 0;
+    S->mrow[e + 1] = (int32_t)(at + c);
+    for (int32_t p = S->rowptr[k]; p < S->rowptr[k + 1]; ++p) {
+      const int32_t j = S->colind[p];
+      if (S->mask[j]) {
+        S->mcol[at] = j;
+        mv[at] = A.vals[p];
+        ++at;
+      }
+    }
+  }
+}
 
 // Face of a point: ||P grad q||^2, lower-active, upper-active, active and not
 // binding, and x'(g - b) (twice q(x)).
@@ -542,7 +608,7 @@ __device__ __forceinline__ void la_compute(const QPStatic *__restrict__ S, int c
 // One pass over the unknowns [k0, k1) of a tile (the list entries [k0, k1)
 // for a CG iteration of the list form).  `slots` are the QP's tile slots: the
 // list pass reads the free counts the set-up pass left at parity lpar.
-template <typename CT, bool PRE, bool LA>
+template <typename CT, bool PRE, bool LA, bool MAT>
 __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restrict__ slots,
                          const QPCore &d, int phase, int lpar, int64_t k0, int64_t k1,
                          double (&acc)[kNP], float (&accf)[2]) {
@@ -618,7 +684,8 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       const OpView<CT> A = op_view<CT>(S);
       uint8_t *__restrict__ mask = S->mask;
       // the first CG iteration runs in the next launch, which reads parity
-      // lpar ^ 1 (in the list form, two launches later: parity lpar)
+      // lpar ^ 1 (in the list form two launches later, in the matrix form
+      // four: parity lpar)
       const int fp = S->list ? lpar : lpar ^ 1;
       CT *__restrict__ r0 = (CT *)S->rho[fp];
       CT *__restrict__ u0 = (CT *)S->uq[fp];
@@ -689,6 +756,18 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       if (fr) S->list[s_base + off + rank] = (int32_t)k;
       __syncthreads();
     } break;
+    case PH_CG_MCOUNT: {
+      // matrix form: nonzeros of A_F, i.e. the free columns of the free rows
+      // (entries [k0, k1) of the list; slot 0, exact integers in FP64)
+      if constexpr (MAT) {
+        const int64_t e1 = k1 < d.m_free ? k1 : d.m_free;
+        for (int64_t e = k0 + threadIdx.x; e < e1; e += st)
+          acc[0] += (double)free_cols(S, S->list[e]);
+      }
+    } break;
+    case PH_CG_MFILL:
+      if constexpr (MAT) matrix_fill<CT>(S, slots, d.m_free, lpar, k0, k1);
+      break;
     case PH_CG_ITER: {
       const OpView<CT> A = op_view<CT>(S);
       const uint8_t *__restrict__ mask = S->mask;
@@ -714,6 +793,7 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       };
       CT gam = CT(0), del = CT(0);
       const int32_t *__restrict__ list = S->list;
+      const int32_t *__restrict__ mrow = S->mrow;
       // list form: entries [k0, k1) of the free list; mask form: rows [k0, k1)
       const int64_t e1 = list ? (k1 < d.m_free ? k1 : d.m_free) : k1;
       for (int64_t e = k0 + threadIdx.x; e < e1; e += st) {
@@ -731,7 +811,14 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
         p[k] = pk;
         sn[k] = sk;
         rn[k] = r1;
-        const CT u1 = apply_row<CT>(A, k, znew);
+        CT u1;
+        if (MAT && mrow) {  // A_F: the free columns only (the others hold z = 0)
+          const CT *__restrict__ mv = (const CT *)S->mval;
+          u1 = CT(0);
+          for (int32_t q = mrow[e]; q < mrow[e + 1]; ++q) u1 = fmaT<CT>(mv[q], znew(S->mcol[q]), u1);
+        } else {
+          u1 = apply_row<CT>(A, k, znew);
+        }
         un[k] = u1;
         gam = fmaT<CT>(r1, z1, gam);
         del = fmaT<CT>(z1, u1, del);
@@ -777,7 +864,8 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
 
 __device__ __forceinline__ int time_bucket(int phase) {
   switch (phase) {
-    case PH_CG_INIT: case PH_CG_LIST: case PH_CG_ITER: return TB_CG;
+    case PH_CG_INIT: case PH_CG_LIST: case PH_CG_MCOUNT: case PH_CG_MFILL: case PH_CG_ITER:
+      return TB_CG;
     case PH_GP_ALPHA: case PH_GP_TRIAL: return TB_GP;
     case PH_PS_TRIAL: return TB_SEARCH;
     default: return TB_OTHER;
@@ -913,12 +1001,20 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R, bool l
       }
     } break;
     case PH_CG_LIST:
+      d.phase = S->mrow ? PH_CG_MCOUNT : PH_CG_ITER;
+      break;
+    case PH_CG_MCOUNT:
+      d.nnz_free = (int64_t)R[0];
+      d.phase = PH_CG_MFILL;
+      break;
+    case PH_CG_MFILL:
       d.phase = PH_CG_ITER;
       break;
     case PH_CG_ITER: {
       d.cg_j += 1;
       d.cg_iters += 1;
       d.cg_free_rows += d.m_free;  // unknowns this CG pass swept with full traffic
+      d.cg_free_nnz += d.nnz_free;
       const double dec = 0.5 * d.cg_alpha * d.gamma;  // q_k(w_{j-1}) - q_k(w_j)
       // eq. (cgstop1), or the residual test ||rho_j|| <= eta ||rho_0|| (M^-1 norm
       // with the preconditioner: gamma = rho'z)
@@ -1220,7 +1316,7 @@ __device__ __forceinline__ void gp_pass_prefetched(const QPStatic *S, const QPCo
 // Stepped form: one launch = one pass of every QP of the launch; one
 // workgroup = one tile.  Every workgroup first folds the previous launch's
 // partial sums into its own copy of the state.
-template <typename CT, bool SPEC, bool PRE>
+template <typename CT, bool SPEC, bool PRE, bool MAT = false>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ QPStatic ss;
@@ -1287,7 +1383,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     } else if (SPEC && gcp == sd.c.cur && (phase == PH_GP_ALPHA || phase == PH_GP_TRIAL)) {
       gp_pass_prefetched(S, sd.c, phase, kk, own, G, acc);
     } else {
-      run_pass<CT, PRE, true>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT, PRE, true, MAT>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
     }
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     __syncthreads();
@@ -1391,7 +1487,7 @@ static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 // workgroups stay in flight); kPartRest every pass but those.
 constexpr int kPartAll = 0, kPartCG = 1, kPartRest = 2;
 
-template <typename CT, bool SPEC, bool PRE, int PART = kPartAll>
+template <typename CT, bool SPEC, bool PRE, int PART = kPartAll, bool MAT = false>
 __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
   __shared__ QPStatic ss;
@@ -1463,7 +1559,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     float accf[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-    run_pass<CT, PRE, false>(S, slots, sc, phase, par, k0, k1, acc, accf);
+    run_pass<CT, PRE, false, MAT>(S, slots, sc, phase, par, k0, k1, acc, accf);
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
   }
@@ -1515,7 +1611,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
       float accf[2] = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
-      run_pass<CT, PRE, false>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
+      run_pass<CT, PRE, false, true>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
       write_partial(slots, par ^ 1, phase, f32_slots(S->mixed, phase), tile, acc, accf);
       __syncthreads();
     }
@@ -1699,6 +1795,13 @@ using namespace gpcg;
 // variant: kVarSpec | kVarPre bits
 void *gpcg_step_kernel_ptr(int mixed, int variant) {
   const bool sp = variant & kVarSpec, pr = variant & kVarPre;
+  if (variant & kVarMat) {
+    if (mixed)
+      return pr ? (void *)&step_kernel<float, false, true, true>
+                : (void *)&step_kernel<float, false, false, true>;
+    return pr ? (void *)&step_kernel<double, false, true, true>
+              : (void *)&step_kernel<double, false, false, true>;
+  }
   if (mixed) {
     if (sp) return pr ? (void *)&step_kernel<float, true, true> : (void *)&step_kernel<float, true, false>;
     return pr ? (void *)&step_kernel<float, false, true> : (void *)&step_kernel<float, false, false>;
@@ -1734,6 +1837,15 @@ void *gpcg_transition_kernel_ptr() { return (void *)&transition_kernel; }
 template <int PART>
 static void *pass_ptr(int mixed, int variant) {
   const bool sp = variant & kVarSpec, pr = variant & kVarPre;
+  if constexpr (PART != kPartCG) {
+    if (variant & kVarMat) {
+      if (mixed)
+        return pr ? (void *)&pass_kernel<float, false, true, PART, true>
+                  : (void *)&pass_kernel<float, false, false, PART, true>;
+      return pr ? (void *)&pass_kernel<double, false, true, PART, true>
+                : (void *)&pass_kernel<double, false, false, PART, true>;
+    }
+  }
   if (mixed) {
     if (sp)
       return pr ? (void *)&pass_kernel<float, true, true, PART>
@@ -1756,7 +1868,7 @@ void *gpcg_pass_kernel_ptr(int mixed, int variant) {
 // The kernel of the passes the CG kernel skips: the early CG loads are of no
 // use there.
 void *gpcg_rest_kernel_ptr(int mixed, int variant) {
-  return pass_ptr<kPartRest>(mixed, variant & kVarPre);
+  return pass_ptr<kPartRest>(mixed, variant & (kVarPre | kVarMat));
 }
 
 int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {

@@ -90,9 +90,10 @@ int validate_opt(const gpcg_options *o) {
     return fail(GPCG_ERR_ARG, "iteration caps must be positive");
   if (o->precision != GPCG_PREC_FP64 && o->precision != GPCG_PREC_MIXED)
     return fail(GPCG_ERR_ARG, "unknown precision");
-  if (o->free_set == GPCG_FREESET_LIST && o->tile != 0 && o->tile != kBlock)
-    return fail(GPCG_ERR_ARG, "the list free set needs 256-unknown tiles");
-  if (o->free_set != GPCG_FREESET_MASK && o->free_set != GPCG_FREESET_LIST)
+  if (o->free_set != GPCG_FREESET_MASK && o->tile != 0 && o->tile != kBlock)
+    return fail(GPCG_ERR_ARG, "the list and matrix free sets need 256-unknown tiles");
+  if (o->free_set != GPCG_FREESET_MASK && o->free_set != GPCG_FREESET_LIST &&
+      o->free_set != GPCG_FREESET_MATRIX)
     return fail(GPCG_ERR_ARG, "unknown free-set mode");
   if (o->tile < 0 || o->tile % kBlock != 0 || o->tile > (1 << 16))
     return fail(GPCG_ERR_ARG, "tile must be a multiple of 256 in [256, 65536]");
@@ -116,6 +117,13 @@ int validate_opt(const gpcg_options *o) {
   return GPCG_OK;
 }
 
+// Options that depend on the operator.
+int validate_pair(const gpcg_operator *op, const gpcg_options &o) {
+  if (o.free_set == GPCG_FREESET_MATRIX && op->kind != GPCG_OP_CSR)
+    return fail(GPCG_ERR_ARG, "the matrix free set needs a CSR operator");
+  return GPCG_OK;
+}
+
 // The fused form sums every tile slot of the previous pass in every
 // workgroup; beyond this many 256-unknown tiles the split form is cheaper.
 constexpr int kFusedMaxTiles = 1024;
@@ -132,7 +140,7 @@ int tuned_tile(int64_t n) { return n > (int64_t)kFusedMaxTiles * kBlock ? 2 * kB
 
 struct Layout {
   size_t qp, slots, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;
-  size_t wx32, wy32, vals32, list, dinv, total;
+  size_t wx32, wy32, vals32, list, mrow, mcol, mval, dinv, total;
   int tile, ntiles;
 };
 
@@ -144,9 +152,9 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free
   const int64_t n = op_n(op);
   const bool mixed = precision == GPCG_PREC_MIXED;
   const size_t ct = mixed ? 4 : 8;
-  // the list form compacts the free set tile by tile with one unknown per
-  // thread: it keeps 256-unknown tiles at every size
-  L.tile = tile_opt > 0 ? tile_opt : (free_set == GPCG_FREESET_LIST ? kBlock : tuned_tile(n));
+  // the list and matrix forms compact the free set tile by tile with one
+  // unknown per thread: they keep 256-unknown tiles at every size
+  L.tile = tile_opt > 0 ? tile_opt : (free_set != GPCG_FREESET_MASK ? kBlock : tuned_tile(n));
   L.ntiles = (int)((n + L.tile - 1) / L.tile);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -175,7 +183,12 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free
     L.wy32 = take(4 * (size_t)(op->ny + 1) * op->nx);
   }
   if (mixed && op->kind == GPCG_OP_CSR) L.vals32 = take(4 * (size_t)op->nnz);
-  L.list = free_set == GPCG_FREESET_LIST ? take(4 * (size_t)n) : 0;
+  const bool matrix = free_set == GPCG_FREESET_MATRIX && op->kind == GPCG_OP_CSR;
+  L.list = free_set != GPCG_FREESET_MASK ? take(4 * (size_t)n) : 0;
+  // matrix form: A_F as CSR (row pointers over the list, at most nnz entries)
+  L.mrow = matrix ? take(4 * ((size_t)n + 1)) : 0;
+  L.mcol = matrix ? take(4 * (size_t)op->nnz) : 0;
+  L.mval = matrix ? take(ct * (size_t)op->nnz) : 0;
   // the constant stencil has a constant diagonal: Jacobi scaling leaves the
   // CG iterates unchanged there, so it is not applied
   L.dinv = precond == GPCG_PRECOND_JACOBI && op->kind != GPCG_OP_STENCIL5_CONST
@@ -270,7 +283,17 @@ double solve_bytes(const QPStatic &s, const QPDyn &dy) {
     B += (double)d.cg_free_rows * c;
     B += dy.pass_count[PH_CG_INIT] * mean_m * c;
   }
-  if (s.list) {
+  if (s.mrow) {
+    // matrix form: per free row the vectors, its list index and row pointer;
+    // per nonzero of A_F a column index and a value; the count and fill passes
+    // read the list, the CSR row pointers and (about five per row) the column
+    // indices and mask bytes, and the fill pass writes A_F
+    const double nnz_f = it > 0 ? (double)d.cg_free_nnz / it : 0.0;
+    B += (double)d.cg_free_rows * (10 * c + 8.0) + (double)d.cg_free_nnz * (4.0 + c);
+    B += dy.pass_count[PH_CG_LIST] * (n * 1.0 + mean_m * 4.0);
+    B += dy.pass_count[PH_CG_MCOUNT] * mean_m * (12.0 + 5.0 * 5.0);
+    B += dy.pass_count[PH_CG_MFILL] * (mean_m * (16.0 + 5.0 * 17.0) + nnz_f * (4.0 + c));
+  } else if (s.list) {
     // list form: the index of each free row instead of the mask of every row;
     // the list pass reads the mask and writes the list
     B += (double)d.cg_free_rows * (10 * c + coefc + 4.0);
@@ -503,7 +526,7 @@ struct gpcg_handle_s {
 namespace {
 
 TuneKey tune_key(const gpcg_handle_s *h) {
-  return TuneKey{h->op.kind, h->st.nx, h->st.ny, h->st.mixed, h->st.list ? 1 : 0,
+  return TuneKey{h->op.kind, h->st.nx, h->st.ny, h->st.mixed, h->st.mrow ? 2 : h->st.list ? 1 : 0,
                  h->st.dinv ? 1 : 0, h->st.tile, h->st.n,
                  h->op.kind == GPCG_OP_CSR ? h->op.nnz : 0};
 }
@@ -548,6 +571,9 @@ void fill_static(gpcg_handle_s *h) {
   q.wv = ws + L.w;
   q.mask = (uint8_t *)(ws + L.mask);
   q.list = L.list ? (int32_t *)(ws + L.list) : nullptr;
+  q.mrow = L.mrow ? (int32_t *)(ws + L.mrow) : nullptr;
+  q.mcol = L.mcol ? (int32_t *)(ws + L.mcol) : nullptr;
+  q.mval = L.mval ? (void *)(ws + L.mval) : nullptr;
   q.dinv = L.dinv ? (const void *)(ws + L.dinv) : nullptr;
   q.host_flag = h->flag.dev;
   put_options(q, h->opt);
@@ -633,6 +659,8 @@ int gpcg_workspace_bytes(const gpcg_operator *op, const gpcg_options *opt, size_
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
   if (rc) return rc;
+  rc = validate_pair(op, o);
+  if (rc) return rc;
   *bytes = layout_for(op, o.precision, o.tile, o.free_set, o.precond).total;
   return GPCG_OK;
 }
@@ -647,6 +675,8 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   if (opt) o = *opt;
   else gpcg_options_default(&o);
   rc = validate_opt(&o);
+  if (rc) return rc;
+  rc = validate_pair(op, o);
   if (rc) return rc;
   Layout L = layout_for(op, o.precision, o.tile, o.free_set, o.precond);
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
@@ -742,7 +772,7 @@ int gpcg_solve(gpcg_handle h, const double *b, const double *l, const double *u,
   SL.total_tiles = h->L.ntiles;
   const LaunchCfg c = h->cfg;
   const int variant = (c.spec ? kVarSpec : 0) | (h->st.dinv ? kVarPre : 0) |
-                      (c.split && c.cgk ? kVarCgk : 0);
+                      (c.split && c.cgk ? kVarCgk : 0) | (h->st.mrow ? kVarMat : 0);
   SL.tiles_per_wg = c.tiles_per_wg;
   SL.data_grid = (h->L.ntiles + c.tiles_per_wg - 1) / c.tiles_per_wg;
   const int chunk = c.chunk;
@@ -1187,12 +1217,14 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       SL.total_tiles = total;
       SL.tiles_per_wg = T;
       SL.data_grid = nitems;
-      bool sp = b->cfg.spec != 0, pre = false;
+      bool sp = b->cfg.spec != 0, pre = false, mat = false;
       for (int i : active) {
         sp = sp && spec_ok(b->hs[i]->st);
         pre = pre || b->hs[i]->st.dinv != nullptr;
+        mat = mat || b->hs[i]->st.mrow != nullptr;
       }
-      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0);
+      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0) |
+                       (mat ? kVarMat : 0);
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
       if (rc) return rc;
