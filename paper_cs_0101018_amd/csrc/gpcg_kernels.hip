@@ -16,14 +16,17 @@
 //             is skipped when the step is accepted and the phase goes on.
 //   CG_INIT   free mask, rho = -g on F, z = M^-1 rho, u = A z, w = 0
 //             (eqs. (cg), (cg2); M = I, or diag(A) with the Jacobi option)
-//   CG_LIST   list form only: compact the free mask into an index list
+//   CG_LIST   list and matrix forms: compact the free mask into an index list
+//   CG_MCOUNT matrix form (CSR): free columns of the free rows, per list tile
+//   CG_MFILL  matrix form: A_F written as CSR over the list (the paper's
+//             technique 1); the CG iterations then read only its nonzeros
 //   CG_ITER   one CG iteration in the single-reduction form of Chronopoulos
 //             and Gear: s = Ap and p by recurrence, w, rho, z, u = A z, and
 //             the two sums rho'z, z'u (eq. (cgstop1) uses 1/2 alpha rho'z)
 //   PS_TRIAL  x' = P[x + alpha w], g' = Ax' - b, g's, s'As, face of x'
 //             (eq. (cglsstop2)); acceptance is again a flip.
-// Reductions are deterministic: wave64 DPP butterflies and LDS per 256-unknown
-// tile into a fixed slot, then a fixed-order sum over the slots.  Launch
+// Reductions are deterministic: wave64 DPP butterflies and LDS per tile (256
+// or 512 unknowns) into a fixed slot, then a fixed-order sum over the slots.  Launch
 // forms: fused (every workgroup sums the previous pass's slots and runs the
 // scalar transition redundantly -- identical inputs, identical decisions --
 // then its tile of the next pass), split (a transition kernel, then a lean
