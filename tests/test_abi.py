@@ -62,3 +62,28 @@ def test_host_side_validation_without_gpu():
     rc = gpcg.gpcg_server_footprint(ctypes.byref(csr), 0, ctypes.byref(nbytes))
     assert rc == gpcg.GPCG_ERR_ARG
     assert gpcg.status_string(gpcg.GPCG_ERR_NOT_SPD).startswith("operator")
+
+
+def test_free_set_forms_host_checks():
+    """The matrix free set needs a CSR operator and 256-unknown tiles; its
+    workspace holds A_F (row offsets, column indices, values) on top of the
+    list form's."""
+    import paper_cs_0101018_amd as gpcg
+    nbytes = ctypes.c_size_t()
+    stencil = gpcg.gpcg_operator(kind=gpcg.GPCG_OP_STENCIL5_CONST, nx=10, ny=10, w=121.0)
+    opt = gpcg.default_options(free_set=gpcg.GPCG_FREESET_MATRIX)
+    rc = gpcg.gpcg_workspace_bytes(ctypes.byref(stencil), ctypes.byref(opt), ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_ERR_ARG
+    n, nnz = 1000, 4960
+    csr = gpcg.gpcg_operator(kind=gpcg.GPCG_OP_CSR, n=n, nnz=nnz, rowptr=8, colind=8, vals=8)
+    sizes = {}
+    for fs in (gpcg.GPCG_FREESET_MASK, gpcg.GPCG_FREESET_LIST, gpcg.GPCG_FREESET_MATRIX):
+        opt = gpcg.default_options(free_set=fs)
+        rc = gpcg.gpcg_workspace_bytes(ctypes.byref(csr), ctypes.byref(opt), ctypes.byref(nbytes))
+        assert rc == gpcg.GPCG_OK
+        sizes[fs] = nbytes.value
+    assert sizes[gpcg.GPCG_FREESET_LIST] >= sizes[gpcg.GPCG_FREESET_MASK] + 4 * n
+    assert sizes[gpcg.GPCG_FREESET_MATRIX] >= sizes[gpcg.GPCG_FREESET_LIST] + 4 * (n + 1) + 12 * nnz
+    opt = gpcg.default_options(free_set=gpcg.GPCG_FREESET_MATRIX, tile=512)
+    rc = gpcg.gpcg_workspace_bytes(ctypes.byref(csr), ctypes.byref(opt), ctypes.byref(nbytes))
+    assert rc == gpcg.GPCG_ERR_ARG

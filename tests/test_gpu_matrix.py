@@ -87,3 +87,20 @@ def test_matrix_form_in_a_batch():
     batch.close()
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_matrix_form_with_jacobi_and_residual_stop(prec):
+    """The preconditioned CG and the residual stopping test on A_F: bitwise
+    the list form's answer."""
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.varcoef(120, 4, eps=0.5)
+    for opts in ({"precond": gpcg.GPCG_PRECOND_JACOBI},
+                 {"cg_stop": gpcg.GPCG_CGSTOP_RESIDUAL},
+                 {"precond": gpcg.GPCG_PRECOND_JACOBI, "cg_stop": gpcg.GPCG_CGSTOP_RESIDUAL}):
+        xm, gm, sm = G.solve(inst, "csr", precision=prec, free_set=gpcg.GPCG_FREESET_MATRIX,
+                             **opts)
+        xl, gl, sl = G.solve(inst, "csr", precision=prec, free_set=gpcg.GPCG_FREESET_LIST, **opts)
+        assert sm["status"] == sl["status"] == gpcg.GPCG_OK, (sm["status"], sl["status"])
+        assert np.array_equal(xm, xl) and np.array_equal(gm, gl)
+        assert sm["cg_iters"] == sl["cg_iters"]
