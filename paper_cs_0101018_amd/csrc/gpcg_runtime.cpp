@@ -1276,16 +1276,23 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     total += (size_t)b->hs[i]->st.n;
   }
   std::vector<double> first(total), other(total);
+  // two solves per configuration, the faster one counts (the first of a
+  // configuration also builds its graphs)
   auto run = [&](const LaunchCfg &c, double *ms, std::vector<double> &out) -> int {
     const LaunchCfg keep = b->cfg;
     b->cfg = c;
-    for (int i = 0; i < cnt; ++i)
-      HIP_OK(hipMemcpyAsync(probs[i].x, x0s[i], sizeof(double) * (size_t)b->hs[i]->st.n,
-                            hipMemcpyDeviceToDevice, b->stream));
-    HIP_OK(hipStreamSynchronize(b->stream));
-    const double t0 = now_s();
-    const int rc = gpcg_batch_solve(b, probs, GPCG_BATCH_STEPPED, nullptr);
-    *ms = (now_s() - t0) * 1e3;
+    *ms = 1e300;
+    int rc = GPCG_OK;
+    for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
+      for (int i = 0; i < cnt; ++i)
+        HIP_OK(hipMemcpyAsync(probs[i].x, x0s[i], sizeof(double) * (size_t)b->hs[i]->st.n,
+                              hipMemcpyDeviceToDevice, b->stream));
+      HIP_OK(hipStreamSynchronize(b->stream));
+      const double t0 = now_s();
+      rc = gpcg_batch_solve(b, probs, GPCG_BATCH_STEPPED, nullptr);
+      const double t = (now_s() - t0) * 1e3;
+      if (t < *ms) *ms = t;
+    }
     b->cfg = keep;
     if (rc < 0) return rc;
     size_t off = 0;
@@ -1325,11 +1332,6 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
   }
   {
     LaunchCfg c = best;
-    c.cgk = best.cgk ? 0 : 1;
-    if ((rc = consider(c)) < 0) return rc;
-  }
-  {
-    LaunchCfg c = best;
     c.spec = best.spec ? 0 : 1;
     if ((rc = consider(c)) < 0) return rc;
   }
@@ -1343,6 +1345,18 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     c.shrink = sh;
     if ((rc = consider(c)) < 0) return rc;
   }
+  // the CG kernel of its own last, and the schedule again if it is taken
+  {
+    LaunchCfg c = best;
+    c.cgk = best.cgk ? 0 : 1;
+    if ((rc = consider(c)) < 0) return rc;
+  }
+  if (best.cgk)
+    for (int sh : {3, 6, 12}) {
+      LaunchCfg c = best;
+      c.shrink = sh;
+      if ((rc = consider(c)) < 0) return rc;
+    }
   b->cfg = best;
   if (report) {
     report->mismatches = mismatches;
