@@ -1117,6 +1117,7 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->mixed = handles[0]->st.mixed;
   b->cfg = LaunchCfg{1, 1, 1, default_chunk(handles[0]->opt), 3};
   b->cfg.cgk = handles[0]->opt.cg_kernel == GPCG_CGK_ON ? 1 : 0;
+  b->cfg.spec = handles[0]->opt.prefetch == GPCG_PREFETCH_OFF ? 0 : 1;
   int rc = alloc_flag(&b->flags, (size_t)count);
   if (rc) {
     delete b;
