@@ -63,7 +63,8 @@ def test_matrix_form_launch_forms_agree(prec):
         assert st["cg_iters"] == s0["cg_iters"]
 
 
-def test_matrix_form_in_a_batch():
+@pytest.mark.parametrize("mode", [0, 1], ids=["stepped", "persistent"])
+def test_matrix_form_in_a_batch(mode):
     """A batch mixing matrix-form CSR members with mask-form stencil members:
     each answer bitwise equal to the same QP solved alone."""
     import paper_cs_0101018_amd as gpcg
@@ -77,7 +78,7 @@ def test_matrix_form_in_a_batch():
                for i, k, f in zip(insts, kinds, sets)]
     batch = gpcg.Batch(solvers, device=dev)
     data = [(G.to_dev(i.b), G.to_dev(i.l), G.to_dev(i.u), G.to_dev(i.x0)) for i in insts]
-    stats = batch.solve(data, mode=gpcg.GPCG_BATCH_STEPPED)
+    stats = batch.solve(data, mode=mode)
     torch.cuda.synchronize()
     for inst, kind, fs, d, st in zip(insts, kinds, sets, data, stats):
         xa, ga, sa = G.solve(inst, kind, free_set=fs)
