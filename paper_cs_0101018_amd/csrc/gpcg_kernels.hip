@@ -1082,9 +1082,7 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R, bool l
 __device__ __forceinline__ void advance(const QPStatic *S, QPDyn &sd, const double *R,
                                        uint64_t now, bool la) {
   const int ph = sd.c.phase;
-  QPCore c = sd.c;
-  transition(S, c, R, la);
-  sd.c = c;
+  transition(S, sd.c, R, la);
   if (ph >= 0 && ph < PH_COUNT) sd.pass_count[ph] += 1;
   const int bk = time_bucket(ph);
   if (sd.t_last) sd.t_bucket[bk] += now - sd.t_last;
