@@ -1327,16 +1327,18 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   QPDev *q = L.single;
   const int par = L.parity;
   double *slots = tile_slots(q);
+  // the state first (everything waits for the pass it names), then the
+  // slots and the early CG operands
+  copy_dyn(&q->dyn[par], &sd);
+  copy_static(&q->st, &ss);
   double pf[kNP];
-  prefetch_slot(slots, par, pf);  // issued together with the state load
+  prefetch_slot(slots, par, pf);
   const uint64_t clk = wall_clock64();
   // SPEC launches hold only stencil QPs with one unknown per thread
   const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
   const bool own = SPEC && kk < q->st.n;
   CGOperands<CT> P{};
   if (own) cg_prefetch<CT, PRE>(&q->st, par, kk, P);
-  copy_dyn(&q->dyn[par], &sd);
-  copy_static(&q->st, &ss);
   __syncthreads();
   const QPStatic *S = &ss;
   const int ntiles = S->ntiles, mixed = S->mixed;
