@@ -1415,6 +1415,8 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   QPDev *q = L.single ? L.single : L.qps[blockIdx.x];
   const int par = L.parity;
   const double *slots = tile_slots(q);
+  copy_dyn(&q->dyn[par], &sd);  // the state first: everything waits for it
+  copy_static(&q->st, &ss);
   double pf[kNP];
   prefetch_slot(slots, par, pf);
   // one QP (its tile count is a launch argument): the two slots a CG pass
@@ -1431,8 +1433,6 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
     e1[m] = (early && t < nt) ? slots[slot_index(t, par, 1)] : 0.0;
   }
   const uint64_t clk = wall_clock64();
-  copy_dyn(&q->dyn[par], &sd);
-  copy_static(&q->st, &ss);
   __syncthreads();
   const QPStatic *S = &ss;
   if (sd.c.pending) {
