@@ -1366,6 +1366,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   }
   __syncthreads();
   const int phase = sd.c.phase;
+  // the next launch's state: written now (the pass below only reads it)
+  if (tile == 0) {
+    copy_dyn(&sd, &q->dyn[par ^ 1]);
+    if (threadIdx.x == 0 && s_fresh_done && S->host_flag)
+      __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   if (phase != PH_DONE) {
     const int64_t k0 = (int64_t)tile * S->tile;
     const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
@@ -1389,12 +1395,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
       run_pass<CT, PRE, true, MAT>(S, slots, sd.c, phase, par, k0, k1, acc, accf);
     }
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
-    __syncthreads();
-  }
-  if (tile == 0) {
-    copy_dyn(&sd, &q->dyn[par ^ 1]);
-    if (threadIdx.x == 0 && s_fresh_done && S->host_flag)
-      __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
