@@ -1322,9 +1322,19 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ QPStatic ss;
   __shared__ int s_fresh_done;
-  // the fused form runs one QP (L.single); workgroup = tile
-  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  QPDev *q = L.single;
+  // one QP (L.single): workgroup = tile; several QPs: workgroup = one-tile
+  // entry of the item table (every workgroup folds its own QP's slots)
+  const int wg = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  QPDev *q;
+  int tile;
+  if (L.single) {
+    q = L.single;
+    tile = wg;
+  } else {
+    const WgItem it = L.items[wg];
+    q = it.q;
+    tile = it.tile0;
+  }
   const int par = L.parity;
   double *slots = tile_slots(q);
   // the state first (everything waits for the pass it names), then the
@@ -1887,9 +1897,11 @@ int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
 }
 
 int gpcg_launch_step(const StepLaunch &L, int mixed, int spec, void *stream) {
-  if (!L.single || L.total_tiles <= 0) return -1;
+  // one QP: a workgroup per tile; several: a workgroup per one-tile item
+  const int grid = L.single ? L.total_tiles : L.data_grid;
+  if (grid <= 0 || (!L.single && !L.items)) return -1;
   hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_step_kernel_ptr(mixed, spec)),
-                     dim3(L.total_tiles), dim3(kBlock), 0, (hipStream_t)stream, L);
+                     dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, L);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -368,8 +368,9 @@ int build_chain_graph(const StepLaunch &L, int mixed, int spec, int split, int c
       if (!rc) rc = add(gpcg_pass_kernel_ptr(mixed, spec), (unsigned)L.data_grid, arg);
       if (!rc && (spec & kVarCgk))
         rc = add(gpcg_rest_kernel_ptr(mixed, spec), (unsigned)L.data_grid, arg);
-    } else {
-      rc = add(gpcg_step_kernel_ptr(mixed, spec), (unsigned)L.total_tiles, arg);
+    } else {  // one QP: a workgroup per tile; several: one per one-tile item
+      rc = add(gpcg_step_kernel_ptr(mixed, spec),
+               (unsigned)(L.single ? L.total_tiles : L.data_grid), arg);
     }
     if (rc) {
       (void)hipGraphDestroy(g);
@@ -1115,7 +1116,12 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->items = (WgItem *)(b->ws + items_offset(count));
   b->tbytes = need;
   b->mixed = handles[0]->st.mixed;
-  b->cfg = LaunchCfg{1, 1, 1, default_chunk(handles[0]->opt), 3};
+  // stepped batches: the split form unless the members ask for the fused one
+  // (one launch per pass, every workgroup folding its own QP's slots: cheaper
+  // for few small QPs, dearer for many large ones; the autotuner decides)
+  b->cfg = LaunchCfg{handles[0]->opt.form == GPCG_FORM_FUSED ? 0 : 1, 1, 1,
+                     default_chunk(handles[0]->opt), 3};
+  if (handles[0]->opt.tiles_per_wg > 0) b->cfg.tiles_per_wg = handles[0]->opt.tiles_per_wg;
   b->cfg.cgk = handles[0]->opt.cg_kernel == GPCG_CGK_ON ? 1 : 0;
   b->cfg.spec = handles[0]->opt.prefetch == GPCG_PREFETCH_OFF ? 0 : 1;
   int rc = alloc_flag(&b->flags, (size_t)count);
@@ -1197,7 +1203,11 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     std::vector<int> active(cnt);
     for (int i = 0; i < cnt; ++i) active[i] = i;
     const int chunk = b->cfg.chunk;
-    const int T = b->cfg.tiles_per_wg;
+    // the fused form (one launch per pass; every workgroup folds its own QP's
+    // slots) unless chosen otherwise or some QP has too many tiles for it
+    bool split = b->cfg.split != 0;
+    for (int i = 0; i < cnt; ++i) split = split || b->hs[i]->st.ntiles > kFusedMaxTiles;
+    const int T = split ? b->cfg.tiles_per_wg : 1;
     while (!active.empty()) {
       HIP_OK(hipStreamSynchronize(b->stream));  // the staged tables may still be in flight
       pre[0] = 0;
@@ -1224,10 +1234,10 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
         pre = pre || b->hs[i]->st.dinv != nullptr;
         mat = mat || b->hs[i]->st.mrow != nullptr;
       }
-      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0) |
-                       (mat ? kVarMat : 0);
+      const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0) |
+                       (split && b->cfg.cgk ? kVarCgk : 0) | (mat ? kVarMat : 0);
       hipGraphExec_t graph = nullptr;
-      int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
+      int rc = build_chain_graph(SL, b->mixed, spec, split ? 1 : 0, chunk, &graph);
       if (rc) return rc;
       // run until 1/shrink of this launch's tiles belong to finished QPs
       auto enough = [&]() {
@@ -1236,8 +1246,8 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
           if (b->flags.host[i]) done_tiles += b->hs[i]->st.ntiles;
         return (int64_t)b->cfg.shrink * done_tiles >= total;
       };
-      rc = run_until(b->stream, SL, b->mixed, spec, 1, chunk, graph, b->ev, enough, (int64_t)1 << 26,
-                     &launches, &checks);
+      rc = run_until(b->stream, SL, b->mixed, spec, split ? 1 : 0, chunk, graph, b->ev, enough,
+                     (int64_t)1 << 26, &launches, &checks);
       (void)hipGraphExecDestroy(graph);
       if (rc) return rc;
       std::vector<int> still;
@@ -1326,11 +1336,17 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     }
     return GPCG_OK;
   };
-  for (int t : {1, 2, 4}) {
+  {  // launch form: fused (one launch per pass) or split
     LaunchCfg c = best;
-    c.tiles_per_wg = t;
+    c.split = best.split ? 0 : 1;
     if ((rc = consider(c)) < 0) return rc;
   }
+  if (best.split)
+    for (int t : {1, 2, 4}) {
+      LaunchCfg c = best;
+      c.tiles_per_wg = t;
+      if ((rc = consider(c)) < 0) return rc;
+    }
   {
     LaunchCfg c = best;
     c.spec = best.spec ? 0 : 1;
@@ -1347,12 +1363,12 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     if ((rc = consider(c)) < 0) return rc;
   }
   // the CG kernel of its own last, and the schedule again if it is taken
-  {
+  if (best.split) {
     LaunchCfg c = best;
     c.cgk = best.cgk ? 0 : 1;
     if ((rc = consider(c)) < 0) return rc;
   }
-  if (best.cgk)
+  if (best.split && best.cgk)
     for (int sh : {3, 6, 12}) {
       LaunchCfg c = best;
       c.shrink = sh;
@@ -1361,7 +1377,7 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
   b->cfg = best;
   if (report) {
     report->mismatches = mismatches;
-    report->chosen.form = GPCG_FORM_SPLIT;
+    report->chosen.form = best.split ? GPCG_FORM_SPLIT : GPCG_FORM_FUSED;
     report->chosen.tiles_per_wg = best.tiles_per_wg;
     report->chosen.prefetch = best.spec;
     report->chosen.chunk = best.chunk;
@@ -1727,6 +1743,8 @@ int gpcg_server_step(gpcg_server s, int *active) {
     SL.total_tiles = pre[cnt];
     SL.tiles_per_wg = 1;
     SL.data_grid = nitems;
+    // the split form: with requests of up to 1024 tiles resident, the fused
+    // form would have every workgroup of a large request sum all its slots
     for (int k = 0; k < s->opt.quantum; ++k) {
       SL.parity = (int)(s->launches & 1);
       if (gpcg_launch_split(SL, s->opt.precision == GPCG_PREC_MIXED, spec, s->stream) != 0)

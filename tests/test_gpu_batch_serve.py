@@ -37,11 +37,15 @@ def _batch(insts, mode, **opts):
 
 
 @pytest.mark.parametrize("mixed", [0, 1])
-@pytest.mark.parametrize("mode", [0, 1], ids=["stepped", "persistent"])
-def test_batch_equals_alone(mode, mixed):
+@pytest.mark.parametrize("mode,form", [(0, 1), (0, 2), (1, 0)],
+                         ids=["stepped_fused", "stepped_split", "persistent"])
+def test_batch_equals_alone(mode, form, mixed):
+    """Stepped batches in the fused form (one launch per pass, every
+    workgroup folds its own QP's slots) and in the split form, and the
+    persistent form."""
     insts = mix(9, seed=11 + mixed)
-    print(f"batch mode={mode} mixed={mixed} sizes={[i.N for i in insts]}", flush=True)
-    xs, stats = _batch(insts, mode, precision=mixed)
+    print(f"batch mode={mode} form={form} mixed={mixed} sizes={[i.N for i in insts]}", flush=True)
+    xs, stats = _batch(insts, mode, precision=mixed, form=form)
     for inst, x, st in zip(insts, xs, stats):
         xa, ga, sa = solo(inst, precision=mixed)
         assert st["status"] == sa["status"] == 0, (st, sa)
@@ -63,7 +67,23 @@ def test_batch_equals_alone_many_tiles(mixed, cgk):
     insts = [instances.obstacle(300, 4, amplitude=0.4), instances.varcoef(270, 1),
              instances.obstacle(45, 2), instances.obstacle(560, 3)]  # 560^2: 512-unknown tiles
     ck = gpcg.GPCG_CGK_ON if cgk else gpcg.GPCG_CGK_OFF
-    xs, stats = _batch(insts, 0, precision=mixed, cg_kernel=ck)
+    xs, stats = _batch(insts, 0, precision=mixed, cg_kernel=ck, form=gpcg.GPCG_FORM_SPLIT)
+    for inst, x, st in zip(insts, xs, stats):
+        xa, ga, sa = solo(inst, precision=mixed)
+        assert st["status"] == sa["status"] == 0, (st, sa)
+        assert np.array_equal(x, xa), inst.name
+        assert st["cg_iters"] == sa["cg_iters"], inst.name
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_batch_fused_many_tiles(mixed):
+    """The fused form of a stepped batch with members whose slot sums have
+    tails (more tiles than threads per workgroup, 512-unknown tiles): each
+    workgroup folds its own QP's slots; bitwise each QP alone."""
+    import paper_cs_0101018_amd as gpcg
+    insts = [instances.obstacle(300, 4, amplitude=0.4), instances.obstacle(45, 2),
+             instances.obstacle(560, 3), instances.varcoef(130, 5)]
+    xs, stats = _batch(insts, 0, precision=mixed, form=gpcg.GPCG_FORM_FUSED)
     for inst, x, st in zip(insts, xs, stats):
         xa, ga, sa = solo(inst, precision=mixed)
         assert st["status"] == sa["status"] == 0, (st, sa)
