@@ -124,9 +124,9 @@ typedef struct {
                           has at most 1024 tiles of 256 unknowns, else split),
                           GPCG_FORM_FUSED or GPCG_FORM_SPLIT; the answer is
                           bitwise the same in every form                     */
-  int32_t tiles_per_wg; /* split form: consecutive 256-unknown tiles per data
-                          workgroup, 1..64; 0 = 1.  The answer does not
-                          depend on it                                        */
+  int32_t tiles_per_wg; /* split form: consecutive tiles (of `tile` unknowns)
+                          per data workgroup, 1..64; 0 = 1.  The answer does
+                          not depend on it                                    */
   int32_t prefetch;     /* CG operands of stencil QPs loaded before the state
                           is read: GPCG_PREFETCH_AUTO (on), _ON or _OFF.  The
                           answer does not depend on it                        */

@@ -6,8 +6,8 @@
 // over the unknowns of a QP (the initial projection and gradient, the exact
 // step length of a gradient-projection iterate, a trial point of a projected
 // search fused with the gradient at that point, the set-up of a reduced CG
-// solve, one CG iteration).  Each workgroup reduces its 256-unknown tile into
-// a fixed tile slot.  Before the next pass the slots are summed in tile order
+// solve, one CG iteration).  The unknowns are cut into tiles of 256 or 512;
+// each tile's partial sums go to fixed slots of that tile.  Before the next pass the slots are summed in tile order
 // and the scalar transition picks the next pass: in every workgroup of the
 // next launch (fused form) or in a transition kernel (split form).  The
 // kernel boundary is the barrier; the state and the slots are double-buffered
