@@ -236,6 +236,44 @@ def spmv_extras(gpcg, torch, dev, reps=40, grids=(1024, 1600), precs=(0, 1)):
     return out
 
 
+def reduction_extras(gpcg, torch, dev, N=8192, reps=20):
+    """Bandwidth of the projected-gradient reduction (||grad_Omega q||^2 and the
+    face counts; x, l, u, g read once: 32 B per unknown) on an 8192^2 grid,
+    two 2.1 GB sets alternated so that every call reads from HBM.  Each call
+    of gpcg_projected_gradient waits for its result on the host, so the time
+    per call (HIP events around the whole loop) includes that round trip: a
+    lower bound on the kernels' own rate."""
+    op = gpcg.Operator.stencil_const(N, N, float((N + 1) ** 2))
+    s = gpcg.Solver(op, device=dev)
+    n = N * N
+    sets = []
+    for k in range(2):
+        g = torch.Generator(device=dev)
+        g.manual_seed(k)
+        lo = torch.rand(n, dtype=torch.float64, device=dev, generator=g) - 0.5
+        up = lo + 0.25 + torch.rand(n, dtype=torch.float64, device=dev, generator=g)
+        x = torch.maximum(lo, torch.zeros_like(lo))
+        x = torch.minimum(x, up)
+        gr = torch.randn(n, dtype=torch.float64, device=dev, generator=g)
+        sets.append((x, lo, up, gr))
+    for i in range(2):
+        s.projected_gradient(*sets[i])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        s.projected_gradient(*sets[i % 2])
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    byt = 32.0 * n
+    del sets
+    s.close()
+    return {f"pgrad{N}_fp64_cold": dict(GBs=round(byt / t / 1e9, 1), us=round(t * 1e6, 2),
+                                        bytes_per_var=32, frac=round(byt / t / 1e9 / HBM_PEAK_GBS, 3),
+                                        includes_host_wait=True)}
+
+
 def _dev_instance(inst, gpcg, torch, dev):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     N = inst.N
@@ -618,7 +656,8 @@ def main():
     if args.extras:
         res["extras"] = spmv_extras(gpcg, torch, dev)
     elif not args.no_spmv:
-        res["spmv"] = spmv_extras(gpcg, torch, dev, grids=(1600, 4096), precs=(0,))
+        res["spmv"] = spmv_extras(gpcg, torch, dev, grids=(1600, 4096, 8192), precs=(0,))
+        res["reduction"] = reduction_extras(gpcg, torch, dev)
     solver.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, precond=int(args.precond == "jacobi"),

@@ -101,15 +101,18 @@ def dense_to_csr(D: np.ndarray):
     return rowptr, np.concatenate(cols), np.concatenate(vals)
 
 
-def stencil_csr(N: int, wx: np.ndarray, wy: np.ndarray):
+def stencil_csr(N: int, wx: np.ndarray, wy: np.ndarray, rows=None):
     """Assemble the five-point edge-weight operator as CSR (sorted columns).
 
     Row k = j*N + i: diagonal wx[j,i] + wx[j,i+1] + wy[j,i] + wy[j+1,i];
     off-diagonals -wy[j,i] (row below), -wx[j,i] (left), -wx[j,i+1] (right),
     -wy[j+1,i] (row above), dropped where the neighbour is outside the grid.
+    rows: None (every row) or sorted distinct row indices; the other rows of
+    the n x n result are left empty (a sample of the operator's rows).
     """
     n = N * N
-    jj, ii = np.divmod(np.arange(n, dtype=np.int64), N)
+    k = np.arange(n, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    jj, ii = np.divmod(k, N)
     diag = wx[jj, ii] + wx[jj, ii + 1] + wy[jj, ii] + wy[jj + 1, ii]
     # candidate entries in sorted-column order: S, W, C, E, N
     cand_col = np.stack([
@@ -117,8 +120,9 @@ def stencil_csr(N: int, wx: np.ndarray, wy: np.ndarray):
         (jj + 1) * N + ii], axis=1)
     cand_val = np.stack([
         -wy[jj, ii], -wx[jj, ii], diag, -wx[jj, ii + 1], -wy[jj + 1, ii]], axis=1)
-    valid = np.stack([jj > 0, ii > 0, np.ones(n, bool), ii < N - 1, jj < N - 1], axis=1)
-    counts = valid.sum(axis=1)
+    valid = np.stack([jj > 0, ii > 0, np.ones(len(k), bool), ii < N - 1, jj < N - 1], axis=1)
+    counts = np.zeros(n, dtype=np.int64)
+    counts[k] = valid.sum(axis=1)
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=rowptr[1:])
     colind = cand_col[valid].astype(np.int32)

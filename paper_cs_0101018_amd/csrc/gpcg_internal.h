@@ -173,8 +173,11 @@ void *gpcg_transition_kernel_ptr();
 void *gpcg_pass_kernel_ptr(int mixed, int spec);
 void *gpcg_rest_kernel_ptr(int mixed, int spec);
 int gpcg_launch_split(const gpcg::StepLaunch &L, int mixed, int spec, void *stream);
-int gpcg_launch_spmv(const gpcg::QPDev *dqp, int64_t n, const void *v, void *y,
-                     const uint8_t *mask, int f32, int vec_nx, void *stream);
+// dqp: the QP's device state; S: the host copy of its static part (the same
+// operator); vec_nx: grid width of a stencil operator whose arrays allow
+// 16-byte loads (0: the scalar kernel).
+int gpcg_launch_spmv(const gpcg::QPDev *dqp, const gpcg::QPStatic *S, int64_t n, const void *v,
+                     void *y, const uint8_t *mask, int f32, int vec_nx, void *stream);
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
                       const double *g, double *pg, double *part, double *out4, void *stream);
 int gpcg_launch_convert_f32(const double *src, float *dst, int64_t count, void *stream);

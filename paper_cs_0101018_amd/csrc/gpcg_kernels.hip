@@ -1760,6 +1760,113 @@ __global__ __launch_bounds__(kBlock) void spmv_stencil_kernel(const QPDev *q,
   for (int e = 0; e < V; ++e) __builtin_nontemporal_store(out[e], y + k + e);
 }
 
+// Row-marching variant for grids whose vectors exceed the last-level cache.
+// A workgroup owns a segment of kBlock * V consecutive unknowns of a grid row
+// (thread t: the V unknowns from V t) over R consecutive rows.  Every row of v
+// the segment touches (R + 2 of them, halo rows included) is loaded once, up
+// front, and kept in registers, so each row of v is fetched once per
+// workgroup instead of three times; west and east neighbours come from the
+// adjacent lanes (lanes 0 and 63 load theirs).  Each unknown is evaluated
+// with the expression of spmv_stencil_kernel, so the products are bitwise
+// equal.  Rows past the grid height and columns past its width read as
+// zeros and are not stored.  VARC: edge-weighted operator (a variant of its
+// own, so that the constant stencil keeps its smaller register budget).  The
+// operator view arrives by value (kernel arguments: no dependent load before
+// the first row load).
+template <typename T, int V, int R, bool VARC>
+__global__ __launch_bounds__(kBlock) void spmv_march_kernel(const OpView<T> A,
+                                                            const T *__restrict__ v,
+                                                            T *__restrict__ y,
+                                                            const uint8_t *__restrict__ mask,
+                                                            int nseg) {
+  using VT = typename VecOf<T, V>::type;
+  using MT = typename MaskOf<V>::type;
+  const int32_t nx = A.nx, ny = A.ny;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int seg = tile % nseg, rb = tile / nseg;
+  const int32_t i0 = seg * (kBlock * V) + V * (int32_t)threadIdx.x;
+  const bool act = i0 < nx;
+  const int lane = (int)threadIdx.x & 63;
+  const int32_t r0 = rb * R;
+  T rows[R + 2][V];
+#pragma unroll
+  for (int e = 0; e < R + 2; ++e) {
+    const int32_t j = r0 - 1 + e;
+#pragma unroll
+    for (int c = 0; c < V; ++c) rows[e][c] = T(0);
+    if (act && j >= 0 && j < ny)
+      *reinterpret_cast<VT *>(rows[e]) =
+          *reinterpret_cast<const VT *>(v + (int64_t)j * nx + i0);
+  }
+  // mask bytes of the rows (0 where the row or column is outside the grid:
+  // nothing is stored there)
+  MT mk[R];
+  if (mask) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      const int32_t j = r0 + e;
+      mk[e] = (act && j < ny) ? *reinterpret_cast<const MT *>(mask + (int64_t)j * nx + i0)
+                              : MT(0);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < R; ++e) mk[e] = MT(~MT(0));
+  }
+  // edge weights of y-edges: row j of wy (j = 0 .. ny) joins grid rows j - 1 and j
+  T wyr[VARC ? R + 1 : 1][V];
+  if (VARC) {
+#pragma unroll
+    for (int e = 0; e <= R; ++e) {
+      const int32_t j = r0 + e;
+#pragma unroll
+      for (int c = 0; c < V; ++c) wyr[e][c] = T(0);
+      if (act && j <= ny)
+        *reinterpret_cast<VT *>(wyr[e]) =
+            *reinterpret_cast<const VT *>(A.wy + (int64_t)j * nx + i0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int32_t j = r0 + e;
+    const bool live = act && j < ny;
+    const int64_t k = (int64_t)j * nx + i0;
+    const T *c = rows[e + 1], *s = rows[e], *nn = rows[e + 2];
+    // west / east neighbours from the adjacent lanes; a lane past the grid
+    // width holds zeros, the Dirichlet value east of the last column
+    T wv = __shfl_up(c[V - 1], 1);
+    T ev = __shfl_down(c[0], 1);
+    if (lane == 0) wv = (live && i0 > 0) ? v[k - 1] : T(0);
+    if (lane == 63) ev = (live && i0 + V < nx) ? v[k + V] : T(0);
+    T out[V];
+    if (!VARC) {
+#pragma unroll
+      for (int c2 = 0; c2 < V; ++c2) {
+        const T vW = c2 == 0 ? wv : c[c2 - 1];
+        const T vE = c2 == V - 1 ? ev : c[c2 + 1];
+        out[c2] = A.w * ((c[c2] - vW) + (c[c2] - vE) + ((c[c2] - s[c2]) + (c[c2] - nn[c2])));
+      }
+    } else {
+      const int64_t ex = (int64_t)j * (nx + 1) + i0;
+      T wx[V + 1];
+#pragma unroll
+      for (int c2 = 0; c2 <= V; ++c2) wx[c2] = live ? A.wx[ex + c2] : T(0);
+#pragma unroll
+      for (int c2 = 0; c2 < V; ++c2) {
+        const T vW = c2 == 0 ? wv : c[c2 - 1];
+        const T vE = c2 == V - 1 ? ev : c[c2 + 1];
+        out[c2] = (wx[c2] * (c[c2] - vW) + wx[c2 + 1] * (c[c2] - vE)) +
+                  (wyr[e][c2] * (c[c2] - s[c2]) + wyr[e + 1][c2] * (c[c2] - nn[c2]));
+      }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < V; ++c2)
+      if (((mk[e] >> (8 * c2)) & 0xFF) == 0) out[c2] = T(0);
+    if (live)
+#pragma unroll
+      for (int c2 = 0; c2 < V; ++c2) __builtin_nontemporal_store(out[c2], y + k + c2);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void pgrad_kernel(int64_t n, const double *__restrict__ x,
                                                        const double *__restrict__ l,
                                                        const double *__restrict__ u,
@@ -1912,8 +2019,14 @@ static int grid_for(int64_t n) {
   return (int)g;
 }
 
-int gpcg_launch_spmv(const QPDev *dqp, int64_t n, const void *v, void *y, const uint8_t *mask,
-                     int f32, int vec_nx, void *stream) {
+// The row-marching SpMV kernel is used when v, y and the mask together exceed
+// this many bytes (the MI355X last-level cache); below it the one-row kernel
+// keeps more workgroups in flight and is as fast or faster.
+constexpr int64_t kMarchBytes = 256ll << 20;
+constexpr int kMarchRows = 4;
+
+int gpcg_launch_spmv(const QPDev *dqp, const QPStatic *S, int64_t n, const void *v, void *y,
+                     const uint8_t *mask, int f32, int vec_nx, void *stream) {
   // vec_nx: the grid width of a stencil operator (0 for CSR); the V-wide
   // kernel needs whole vectors per grid row and aligned arrays
   const int V = f32 ? 4 : 2;
@@ -1921,6 +2034,39 @@ int gpcg_launch_spmv(const QPDev *dqp, int64_t n, const void *v, void *y, const 
                        ((uintptr_t)y % (V * (f32 ? 4 : 8))) == 0 &&
                        (!mask || ((uintptr_t)mask % V) == 0);
   if (vec_nx > 0 && vec_nx % V == 0 && aligned) {
+    // vectors beyond the 256 MB last-level cache: each row fetched once
+    const int64_t vec_bytes = n * (int64_t)(2 * (f32 ? 4 : 8) + 1);
+    if (vec_bytes > kMarchBytes) {
+      const int ny = (int)(n / vec_nx);
+      const int nseg = (vec_nx + kBlock * V - 1) / (kBlock * V);
+      const int64_t blocks = (int64_t)nseg * ((ny + kMarchRows - 1) / kMarchRows);
+      if (blocks > 0x7fffffff) return -1;
+      const dim3 g((unsigned)blocks), b(kBlock);
+      const hipStream_t st = (hipStream_t)stream;
+      const bool var_coef = S->op_kind == OPK_VAR;
+      if (f32) {
+        OpView<float> A{};
+        A.kind = S->op_kind; A.nx = S->nx; A.ny = S->ny;
+        A.w = S->w32; A.wx = S->wx32; A.wy = S->wy32;
+        if (var_coef)
+          hipLaunchKernelGGL((spmv_march_kernel<float, 4, kMarchRows, true>), g, b, 0, st, A,
+                             (const float *)v, (float *)y, mask, nseg);
+        else
+          hipLaunchKernelGGL((spmv_march_kernel<float, 4, kMarchRows, false>), g, b, 0, st, A,
+                             (const float *)v, (float *)y, mask, nseg);
+      } else {
+        OpView<double> A{};
+        A.kind = S->op_kind; A.nx = S->nx; A.ny = S->ny;
+        A.w = S->w; A.wx = S->wx; A.wy = S->wy;
+        if (var_coef)
+          hipLaunchKernelGGL((spmv_march_kernel<double, 2, kMarchRows, true>), g, b, 0, st, A,
+                             (const double *)v, (double *)y, mask, nseg);
+        else
+          hipLaunchKernelGGL((spmv_march_kernel<double, 2, kMarchRows, false>), g, b, 0, st, A,
+                             (const double *)v, (double *)y, mask, nseg);
+      }
+      return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     const int64_t groups = n / V;
     const int grid = (int)((groups + kBlock - 1) / kBlock);
     if (f32)

@@ -936,7 +936,8 @@ static int spmv_vec_nx(const gpcg_handle_s *h, int f32) {
 int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
   // the kernel reads the operator from the device state uploaded at create
-  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 0, spmv_vec_nx(h, 0), h->stream))
+  if (gpcg_launch_spmv(h->dqp, &h->st, h->st.n, v, y, mask, 0, spmv_vec_nx(h, 0),
+                       h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
 }
@@ -944,7 +945,8 @@ int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask) {
 int gpcg_spmv_f32(gpcg_handle h, const float *v, float *y, const uint8_t *mask) {
   if (!h || !v || !y) return fail(GPCG_ERR_ARG, "handle, v and y are required");
   if (!h->st.mixed) return fail(GPCG_ERR_ARG, "handle was not created with GPCG_PREC_MIXED");
-  if (gpcg_launch_spmv(h->dqp, h->st.n, v, y, mask, 1, spmv_vec_nx(h, 1), h->stream))
+  if (gpcg_launch_spmv(h->dqp, &h->st, h->st.n, v, y, mask, 1, spmv_vec_nx(h, 1),
+                       h->stream))
     return fail(GPCG_ERR_HIP, "spmv launch failed");
   return GPCG_OK;
 }

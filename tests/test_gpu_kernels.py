@@ -96,6 +96,65 @@ def test_spmv_vector_kernel_bitwise(N, kind, prec):
     s.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", ["const", "var"])
+def test_spmv_row_marching_large_grid(kind, prec):
+    """Grids whose v, y and mask exceed the 256 MB last-level cache take the
+    row-marching kernel (rows of v kept in registers, neighbours from adjacent
+    lanes).  Its product equals the one-row scalar kernel's bitwise (the same
+    arrays at an odd element offset), masked, and the oracle's product on
+    sampled rows: the grid border, the ragged last segment and row block, and
+    rows inside."""
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    # FP64: 17 B per unknown, 4098^2 = 16.8 M unknowns (285 MB), 4098 = 8 * 512 + 2
+    # FP32: 9 B per unknown, 5464^2 = 29.9 M unknowns (269 MB), 5464 = 5 * 1024 + 344
+    N = 5464 if prec else 4098
+    n = N * N
+    print(f"spmv row marching N={N} kind={kind} prec={prec}", flush=True)
+    if kind == "var":
+        wx, wy = instances.varcoef_weights(N)
+        rng_w = np.random.default_rng(5)
+        wx = wx * rng_w.uniform(0.5, 1.5, size=wx.shape)
+        wy = wy * rng_w.uniform(0.5, 1.5, size=wy.shape)
+        op = gpcg.Operator.stencil_var(N, N, G.to_dev(wx.ravel()), G.to_dev(wy.ravel()))
+    else:
+        w = float((N + 1) ** 2)
+        wx, wy = np.full((N, N + 1), w), np.full((N + 1, N), w)
+        op = gpcg.Operator.stencil_const(N, N, w)
+    s = gpcg.Solver(op, device=dev, precision=prec)
+    dt = torch.float32 if prec else torch.float64
+    rng = np.random.default_rng(N + prec)
+    v_np = rng.standard_normal(n).astype(np.float32 if prec else np.float64)
+    m_np = (rng.uniform(size=n) < 0.6).astype(np.uint8)
+    v = torch.from_numpy(v_np).to(dev)
+    m = torch.from_numpy(m_np).to(dev)
+    vb = torch.zeros(n + 1, dtype=dt, device=dev)
+    mb = torch.zeros(n + 1, dtype=torch.uint8, device=dev)
+    vb[1:] = v
+    mb[1:] = m
+    jrows = sorted({0, 1, 2, 3, 4, 5, N // 2 - 1, N // 2, N // 2 + 1, N - 3, N - 2, N - 1})
+    rows = (np.asarray(jrows, dtype=np.int64)[:, None] * N + np.arange(N)[None, :]).ravel()
+    ref = oracle.default().matvec(instances.stencil_csr(N, wx, wy, rows),
+                                  v_np.astype(np.float64))[rows]
+    scale = 4.0 * max(wx.max(), wy.max()) * np.abs(v_np).max()
+    tol = 1e-5 * scale if prec else 8e-14 * scale
+    for mask, mask_odd in ((None, None), (m, mb[1:])):
+        y_vec = torch.empty(n, dtype=dt, device=dev)
+        y_odd = torch.zeros(n + 1, dtype=dt, device=dev)
+        s.spmv(v, y_vec, mask)
+        s.spmv(vb[1:], y_odd[1:], mask_odd)
+        torch.cuda.synchronize()
+        assert torch.equal(y_vec, y_odd[1:])
+        got = y_vec.cpu().numpy().astype(np.float64)[rows]
+        want = ref if mask is None else ref * m_np[rows]
+        if mask is not None:
+            assert np.all(got[m_np[rows] == 0] == 0.0)
+        assert np.abs(got - want).max() <= tol
+        del y_vec, y_odd
+    s.close()
+
+
 @pytest.mark.parametrize("n", [1, 255, 256, 257, 5000, 70001])
 def test_projected_gradient_exact(n):
     """Projected gradient and face counts are compare/select work: bit-exact."""
