@@ -511,6 +511,9 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     if args.copy_calib:
+        # the calibration copy must be the largest copy of the run: no SpMV
+        # bandwidth figure (its reference copies reach 512 MiB)
+        args.no_spmv = True
         a = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
