@@ -1867,22 +1867,43 @@ __global__ __launch_bounds__(kBlock) void spmv_march_kernel(const OpView<T> A,
   }
 }
 
+// kPgradUnroll unknowns per thread and loop trip (k, k + 256, ...): their
+// loads are issued together, at clamped in-range indices, before any is used,
+// so each thread keeps 4 * kPgradUnroll loads in flight.
+constexpr int kPgradUnroll = 4;
+
 __global__ __launch_bounds__(kBlock) void pgrad_kernel(int64_t n, const double *__restrict__ x,
                                                        const double *__restrict__ l,
                                                        const double *__restrict__ u,
                                                        const double *__restrict__ g,
                                                        double *__restrict__ pg,
                                                        double *__restrict__ part) {
+  constexpr int U = kPgradUnroll;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * kBlock) {
-    const double xk = x[k], lk = l[k], uk = u[k], gk = g[k];
-    const double p = proj_grad(xk, lk, uk, gk);
-    if (pg) pg[k] = p;
-    acc[0] = __fma_rn(p, p, acc[0]);
-    acc[1] += (xk == lk) ? 1.0 : 0.0;
-    acc[2] += (xk != lk && xk == uk) ? 1.0 : 0.0;
-    acc[3] += (is_active(xk, lk, uk) && !is_binding(xk, lk, uk, gk)) ? 1.0 : 0.0;
+  const int64_t step = (int64_t)gridDim.x * kBlock * U;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock * U + threadIdx.x; base < n; base += step) {
+    double xv[U], lv[U], uv[U], gv[U];
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      const int64_t k = base + (int64_t)e * kBlock;
+      const int64_t kc = k < n ? k : n - 1;
+      xv[e] = x[kc];
+      lv[e] = l[kc];
+      uv[e] = u[kc];
+      gv[e] = g[kc];
+    }
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      const int64_t k = base + (int64_t)e * kBlock;
+      if (k >= n) break;
+      const double xk = xv[e], lk = lv[e], uk = uv[e], gk = gv[e];
+      const double p = proj_grad(xk, lk, uk, gk);
+      if (pg) pg[k] = p;
+      acc[0] = __fma_rn(p, p, acc[0]);
+      acc[1] += (xk == lk) ? 1.0 : 0.0;
+      acc[2] += (xk != lk && xk == uk) ? 1.0 : 0.0;
+      acc[3] += (is_active(xk, lk, uk) && !is_binding(xk, lk, uk, gk)) ? 1.0 : 0.0;
+    }
   }
   block_sum<double, 4>(acc);
   if (threadIdx.x == 0)
@@ -2089,7 +2110,8 @@ int gpcg_launch_spmv(const QPDev *dqp, const QPStatic *S, int64_t n, const void 
 
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
                       const double *g, double *pg, double *part, double *out4, void *stream) {
-  int grid = grid_for(n);
+  if (n <= 0) return -1;
+  int grid = grid_for((n + kPgradUnroll - 1) / kPgradUnroll);
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x, l, u,
                      g, pg, part);
