@@ -660,6 +660,8 @@ def main():
         res["extras"] = spmv_extras(gpcg, torch, dev)
     elif not args.no_spmv:
         res["spmv"] = spmv_extras(gpcg, torch, dev, grids=(1600, 4096, 8192), precs=(0,))
+        # the FP32 product of the mixed form on the grid beyond the last-level cache
+        res["spmv"].update(spmv_extras(gpcg, torch, dev, grids=(8192,), precs=(1,)))
         res["reduction"] = reduction_extras(gpcg, torch, dev)
     solver.close()
     if not args.no_cpu_baseline:
