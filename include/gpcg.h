@@ -244,7 +244,10 @@ int gpcg_destroy(gpcg_handle h);
  * FP64.  mask: NULL or a device byte array; where mask[k] == 0 the result is
  * 0 (the reduced product Z Z' A Z Z' v used by the CG phase).  v and y are
  * device arrays of length n that must not overlap.  Stream-ordered on the
- * handle's stream; does not wait. */
+ * handle's stream; does not wait.  The library picks the kernel by layout and
+ * size (stencils: 16-byte loads when the grid width and the arrays allow it;
+ * v, y and mask above 256 MB: rows kept in registers); every choice gives
+ * bitwise the same product. */
 int gpcg_spmv(gpcg_handle h, const double *v, double *y, const uint8_t *mask);
 
 /* Same in FP32 for a handle created with GPCG_PREC_MIXED (the FP32 copy of
