@@ -155,7 +155,41 @@ def test_spmv_row_marching_large_grid(kind, prec):
     s.close()
 
 
-@pytest.mark.parametrize("n", [1, 255, 256, 257, 5000, 70001])
+def test_spmv_bench_size_8192():
+    """The SpMV bandwidth figure's largest grid (8192^2, constant stencil, FP64,
+    mask of ones as timed): the row-marching product equals the one-row
+    kernel's bitwise and the oracle's product on sampled rows."""
+    import paper_cs_0101018_amd as gpcg
+    torch, dev = G.torch_dev()
+    N = 8192
+    n = N * N
+    print(f"spmv bench size N={N}", flush=True)
+    w = float((N + 1) ** 2)
+    s = gpcg.Solver(gpcg.Operator.stencil_const(N, N, w), device=dev)
+    v = torch.randn(n, dtype=torch.float64, device=dev)
+    m = torch.ones(n, dtype=torch.uint8, device=dev)
+    y = torch.empty_like(v)
+    s.spmv(v, y, m)
+    vb = torch.zeros(n + 1, dtype=torch.float64, device=dev)
+    mb = torch.zeros(n + 1, dtype=torch.uint8, device=dev)
+    vb[1:] = v
+    mb[1:] = m
+    y_odd = torch.zeros(n + 1, dtype=torch.float64, device=dev)
+    s.spmv(vb[1:], y_odd[1:], mb[1:])
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_odd[1:])
+    del vb, mb, y_odd
+    jrows = [0, 1, 3, 4, 5, N // 2, N - 5, N - 4, N - 1]
+    rows = (np.asarray(jrows, dtype=np.int64)[:, None] * N + np.arange(N)[None, :]).ravel()
+    wx, wy = np.full((N, N + 1), w), np.full((N + 1, N), w)
+    v_np = v.cpu().numpy()
+    ref = oracle.default().matvec(instances.stencil_csr(N, wx, wy, rows), v_np)[rows]
+    got = y.cpu().numpy()[rows]
+    assert np.abs(got - ref).max() <= 8e-14 * 4.0 * w * np.abs(v_np).max()
+    s.close()
+
+
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 5000, 70001, 5_000_001])
 def test_projected_gradient_exact(n):
     """Projected gradient and face counts are compare/select work: bit-exact."""
     import paper_cs_0101018_amd as gpcg
