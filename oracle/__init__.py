@@ -56,11 +56,14 @@ class Stats(C.Structure):
                 ("tau", C.c_double), ("q", C.c_double), ("n_free", C.c_int64),
                 ("n_lower", C.c_int64), ("n_upper", C.c_int64),
                 ("trace_q", C.c_void_p), ("trace_act", C.c_void_p),
-                ("trace_cap", C.c_int32), ("trace_len", C.c_int32)]
+                ("trace_cap", C.c_int32), ("trace_len", C.c_int32),
+                ("trace_cg_eta", C.c_void_p), ("trace_cg_iters", C.c_void_p),
+                ("trace_cg_repeat", C.c_void_p), ("trace_cg_dec", C.c_void_p),
+                ("trace_cg_cap", C.c_int32), ("trace_cg_len", C.c_int32),
+                ("trace_dec_per", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_
-                if k not in ("trace_q", "trace_act", "trace_cap", "trace_len")}
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("trace_")}
 
 
 def build(out: Optional[str] = None, mutant: int = 0) -> str:
@@ -209,8 +212,15 @@ class Oracle:
         return st, d, it.value, decs[:min(it.value, dec_cap)]
 
     # -- the whole method
-    def gpcg(self, csr, b, l, u, x0, trace_cap: int = 0, **opts):
-        """Run Algorithm GPCG; returns (x, g, stats-dict[, q trace])."""
+    def gpcg(self, csr, b, l, u, x0, trace_cap: int = 0, cg_trace_cap: int = 0,
+             dec_per: int = 64, **opts):
+        """Run Algorithm GPCG; returns (x, g, stats-dict).
+
+        trace_cap > 0 adds ``trace_q`` and ``trace_act`` (one entry per
+        projected search); cg_trace_cap > 0 adds ``cg_phases_trace``: per CG
+        phase the eta of its stopping test, its iterations, whether it repeats
+        CG on the previous face (eq. (cgstop3)), and its first dec_per CG
+        decreases."""
         A, keep = self._csr(csr)
         b, l, u, x0 = _f64(b), _f64(l), _f64(u), _f64(x0)
         x = np.empty_like(x0)
@@ -223,12 +233,31 @@ class Oracle:
             st.trace_q = trace.ctypes.data
             st.trace_act = trace_act.ctypes.data
             st.trace_cap = trace_cap
+        ccap = max(cg_trace_cap, 1)
+        cg_eta = np.zeros(ccap)
+        cg_it = np.zeros(ccap, dtype=np.int32)
+        cg_rep = np.zeros(ccap, dtype=np.int32)
+        cg_dec = np.full(ccap * dec_per, np.nan)
+        if cg_trace_cap:
+            st.trace_cg_eta = cg_eta.ctypes.data
+            st.trace_cg_iters = cg_it.ctypes.data
+            st.trace_cg_repeat = cg_rep.ctypes.data
+            st.trace_cg_dec = cg_dec.ctypes.data
+            st.trace_cg_cap = cg_trace_cap
+            st.trace_dec_per = dec_per
         self.lib.ora_gpcg(C.byref(A), _ptr(b), _ptr(l), _ptr(u), _ptr(x0), C.byref(o),
                           _ptr(x), _ptr(g), C.byref(st))
         out = st.as_dict()
         if trace_cap:
             out["trace_q"] = trace[:st.trace_len].copy()
             out["trace_act"] = trace_act[:2 * st.trace_len].reshape(-1, 2).copy()
+        if cg_trace_cap:
+            k = st.trace_cg_len
+            decs = cg_dec.reshape(ccap, dec_per)
+            out["cg_phases_trace"] = [
+                dict(eta=float(cg_eta[i]), iters=int(cg_it[i]), repeat=int(cg_rep[i]),
+                     decs=decs[i, :min(int(cg_it[i]), dec_per)].copy())
+                for i in range(k)]
         return x, g, out
 
     def solve_instance(self, inst, **opts):

@@ -98,6 +98,15 @@ typedef struct {
   int64_t *trace_act; /* optional: |A(x)| before each CG phase and after
                          the projected search that follows it (2 per entry) */
   int32_t trace_cap, trace_len;
+  /* optional trace of the CG phases, one entry per phase: the eta its
+   * stopping test used, its CG iterations, 1 when it repeats CG on the face
+   * of the previous phase (eq. (cgstop3)) and 0 when a gradient-projection
+   * phase ran before it, and its CG decreases (the first trace_dec_per of
+   * each phase, at trace_cg_dec[phase * trace_dec_per]) */
+  double *trace_cg_eta;
+  int32_t *trace_cg_iters, *trace_cg_repeat;
+  double *trace_cg_dec;
+  int32_t trace_cg_cap, trace_cg_len, trace_dec_per;
 } ora_stats;
 
 void ora_default_options(ora_options *o) {
@@ -150,7 +159,11 @@ void ora_gradient(const ora_csr *A, const double *x, const double *b, double *g)
 double ora_objective(const ora_csr *A, const double *b, const double *x) {
   double *Ax = (double *)malloc(sizeof(double) * (size_t)(A->n > 0 ? A->n : 1));
   ora_matvec(A, x, Ax);
+#if ORA_MUTANT == 17
+  double q = ora_dot(A->n, x, Ax) - ora_dot(A->n, b, x);
+#else
   double q = 0.5 * ora_dot(A->n, x, Ax) - ora_dot(A->n, b, x);
+#endif
   free(Ax);
   return q;
 }
@@ -405,7 +418,11 @@ int ora_reduced_cg(const ora_csr *A, const unsigned char *free_mask, const doubl
       if (cg_stop == 1) stop = stop || (sqrt(rz_new) <= eta * sqrt(rz0));
 #endif
       else stop = stop || (j >= 2 && dec <= eta * decmax);
+#if ORA_MUTANT == 13
+      if (j == 1) decmax = dec;
+#else
       if (dec > decmax) decmax = dec;
+#endif
       if (stop) break;
 #if ORA_MUTANT == 5
       double beta = rz / rz_new;
@@ -465,13 +482,17 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
   if (opt_in) opt = *opt_in;
   else ora_default_options(&opt);
   int64_t n = A->n;
-  double *trace_q = st->trace_q;
-  int64_t *trace_act = st->trace_act;
-  int32_t trace_cap = st->trace_cap;
+  ora_stats keep = *st; /* the caller's trace buffers survive the reset */
   memset(st, 0, sizeof(*st));
-  st->trace_q = trace_q;
-  st->trace_act = trace_act;
-  st->trace_cap = trace_cap;
+  st->trace_q = keep.trace_q;
+  st->trace_act = keep.trace_act;
+  st->trace_cap = keep.trace_cap;
+  st->trace_cg_eta = keep.trace_cg_eta;
+  st->trace_cg_iters = keep.trace_cg_iters;
+  st->trace_cg_repeat = keep.trace_cg_repeat;
+  st->trace_cg_dec = keep.trace_cg_dec;
+  st->trace_cg_cap = keep.trace_cg_cap;
+  st->trace_dec_per = keep.trace_dec_per;
   if (n <= 0) return st->status = ORA_ERR_ARG;
   if (has_nan(n, b) || has_nan(n, l) || has_nan(n, u) || has_nan(n, x0))
     return st->status = ORA_ERR_NAN;
@@ -502,6 +523,12 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
   if (pgn <= tau) goto done;
   double best_pg = pgn;
   int32_t stall = 0;
+#if ORA_MUTANT == 14
+  const double eta_gp = opt.eta2, eta_cg0 = opt.eta1;
+#else
+  const double eta_gp = opt.eta1, eta_cg0 = opt.eta2;
+#endif
+  double eta = eta_cg0;
 
   for (;;) {
     /* ---- gradient-projection phase, eqs. (next-y)-(pgstop2) ---- */
@@ -541,7 +568,7 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
         ++st->gp_iters;
         ++gp_accepts;
         double dec = -delta;
-        int stop = (nchg == 0) || (j >= 2 && dec <= opt.eta1 * decmax) || (j >= opt.max_gp);
+        int stop = (nchg == 0) || (j >= 2 && dec <= eta_gp * decmax) || (j >= opt.max_gp);
         if (dec > decmax) decmax = dec;
         if (stop) break;
       }
@@ -550,7 +577,10 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
     }
 
     /* ---- CG on the face, then projected search; repeat while B = A ---- */
-    double eta = opt.eta2;
+#if ORA_MUTANT != 16
+    eta = eta_cg0; /* a gradient-projection phase ran: eta2 starts afresh */
+#endif
+    int repeat = 0;
     for (;;) {
       int64_t m = 0;
       for (int64_t i = 0; i < n; ++i) {
@@ -572,8 +602,20 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
         break;
       }
       int32_t it = 0;
+      const int traced = st->trace_cg_len < st->trace_cg_cap;
+      double *dec_out = NULL;
+      if (traced) {
+        if (st->trace_cg_eta) st->trace_cg_eta[st->trace_cg_len] = eta;
+        if (st->trace_cg_repeat) st->trace_cg_repeat[st->trace_cg_len] = repeat;
+        if (st->trace_cg_dec && st->trace_dec_per > 0)
+          dec_out = st->trace_cg_dec + (int64_t)st->trace_cg_len * st->trace_dec_per;
+      }
       int cgs = ora_reduced_cg(A, fm, g, eta, opt.max_cg, opt.precond, opt.cg_stop, d, &it,
-                               NULL, 0);
+                               dec_out, dec_out ? st->trace_dec_per : 0);
+      if (traced) {
+        if (st->trace_cg_iters) st->trace_cg_iters[st->trace_cg_len] = it;
+        ++st->trace_cg_len;
+      }
       st->cg_iters += it;
       ++st->cg_phases;
       if (cgs != ORA_OK) {
@@ -628,7 +670,10 @@ int ora_gpcg(const ora_csr *A, const double *b, const double *l, const double *u
       int64_t lo, up, nb;
       ora_classify(n, x, l, u, g, &lo, &up, &nb);
       if (nb != 0) break; /* B(x) != A(x): next GPCG iteration starts with GP */
+#if ORA_MUTANT != 15
       eta *= opt.eta2_reduce; /* cgstop3: same face, more accurate CG */
+#endif
+      repeat = 1;
       ++st->face_repeats;
     }
   }

@@ -336,6 +336,209 @@ def pin_residual_cg_stop(o):
     assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
 
 
+
+# ------------------------------------------------------------ stopping rules
+
+def _spd(seed, n=10, decades=4.0):
+    """An SPD matrix with eigenvalues spread over `decades` decades (random
+    orthogonal basis) and a vector g, both from the seed."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(10.0 ** rng.uniform(0.0, decades, n)) @ Q.T
+    return 0.5 * (A + A.T), rng.standard_normal(n)
+
+
+def _direct_decreases(A, g, iterates):
+    """q_k(w_{j-1}) - q_k(w_j) along the iterates, from w_0 = 0, with
+    q_k(w) = 1/2 w'Aw + g'w evaluated directly (not by the CG identity)."""
+    qk = lambda w: 0.5 * w @ (A @ w) + g @ w
+    vals = [0.0] + [qk(w) for w in iterates]
+    return np.array([vals[j] - vals[j + 1] for j in range(len(iterates))])
+
+
+def _ratio_stop(decs, eta, frozen=False):
+    """1-based index of the first j >= 2 with dec_j <= eta * max_{l<j} dec_l,
+    the relative-decrease test of eqs. (pgstop2) and (cgstop1); None when no
+    iterate passes it.  frozen: the misreading that compares with the first
+    decrease instead of the largest earlier one."""
+    for j in range(1, len(decs)):
+        ref = decs[0] if frozen else np.max(decs[:j])
+        if decs[j] <= eta * ref:
+            return j + 1
+    return None
+
+
+# (seed of _spd, eta): cases where the running max and the first decrease give
+# different stopping iterations
+CG_RATIO_CASES = [(0, 0.05), (1, 0.5), (3, 0.5), (4, 0.5), (5, 0.2)]
+
+
+def pin_cg_ratio_stop(o):
+    """Eq. (cgstop1): the reduced CG stops at the first iterate j >= 2 whose
+    decrease q_k(w_{j-1}) - q_k(w_j) is at most eta_2 times the largest
+    earlier decrease.  The decreases come from textbook CG iterates and a
+    direct evaluation of q_k; every case is one where the decreases are not
+    monotone, so comparing with the first decrease would stop elsewhere."""
+    for seed, eta in CG_RATIO_CASES:
+        A, g = _spd(seed)
+        n = len(g)
+        ref = _textbook_cg(A, -g, n)
+        decs = _direct_decreases(A, g, ref)
+        want = _ratio_stop(decs, eta)
+        assert want is not None and want < len(ref), (seed, eta)
+        assert want != _ratio_stop(decs, eta, frozen=True), (seed, eta)
+        for j in range(1, want):  # no decision within rounding of the threshold
+            r = decs[j] / np.max(decs[:j])
+            assert abs(r - eta) > 1e-6 * eta, (seed, eta, j, r)
+        st, d, it, odecs = o.reduced_cg(instances.dense_to_csr(A), np.ones(n, np.uint8), g, eta)
+        assert st == 0 and it == want, (seed, eta, it, want)
+        assert np.allclose(d, ref[it - 1], rtol=1e-8, atol=1e-10 * np.abs(ref[it - 1]).max())
+        assert np.allclose(odecs, decs[:it], rtol=1e-7), (seed, eta)
+
+
+def _proj_grad_def(x, l, u, g):
+    """Eq. (proj-gradient) written out: g_i on free variables, min(g_i, 0) at
+    a lower bound, max(g_i, 0) at an upper bound, 0 when l_i = u_i."""
+    p = g.copy()
+    at_l, at_u = x == l, x == u
+    p[at_l & at_u] = 0.0
+    only_l, only_u = at_l & ~at_u, at_u & ~at_l
+    p[only_l] = np.minimum(g[only_l], 0.0)
+    p[only_u] = np.maximum(g[only_u], 0.0)
+    return p
+
+
+def _gp_phase(A, b, l, u, x, eta1, mu=0.01, max_gp=50, max_backtrack=60):
+    """One gradient-projection phase of Algorithm GPCG, written here from
+    Section 3: y_{j+1} = P[y_j - alpha_j grad q(y_j)] with alpha_j the first
+    of alpha_0, alpha_0/2, ... giving sufficient decrease (eq. (gplsstop),
+    q evaluated directly), alpha_0 the minimiser of q along -P grad q(y_j);
+    stop when the active set repeats (pgstop1), on the relative-decrease test
+    with eta1 (pgstop2), or after max_gp iterates.  Returns (iterates, the
+    decreases, reason, smallest relative margin of a backtracking decision)."""
+    q = lambda v: 0.5 * v @ (A @ v) - b @ v
+    y = np.minimum(np.maximum(x, l), u)
+    decs, margin = [], np.inf
+    while True:
+        g = A @ y - b
+        d = _proj_grad_def(y, l, u, g)
+        if not d.any():
+            return len(decs), decs, "optimal", margin
+        a = (d @ d) / (d @ (A @ d))
+        for _ in range(max_backtrack + 1):
+            yn = np.minimum(np.maximum(y - a * g, l), u)
+            gs = g @ (yn - y)
+            slack = q(yn) - q(y) - mu * gs
+            margin = min(margin, abs(slack) / max(abs(gs), 1e-300))
+            if slack <= 0.0:
+                break
+            a *= 0.5
+        else:
+            return len(decs), decs, "backtrack", margin
+        dec = q(y) - q(yn)
+        same_face = np.array_equal((y == l) | (y == u), (yn == l) | (yn == u))
+        j = len(decs) + 1
+        ratio = dec <= eta1 * max(decs) if decs else False
+        decs.append(dec)
+        y = yn
+        if same_face:
+            return j, decs, "pgstop1", margin
+        if ratio:
+            return j, decs, "pgstop2", margin
+        if j >= max_gp:
+            return j, decs, "cap", margin
+
+
+def _gp_case(seed, n=40):
+    """A dense box-constrained QP started at its upper bounds, where the first
+    gradient-projection phase runs several iterates."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(10.0 ** rng.uniform(0.0, 2.5, n)) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = 20.0 * rng.standard_normal(n)
+    l = rng.uniform(-1.0, 0.0, n)
+    u = l + rng.uniform(0.2, 1.5, n)
+    return A, b, l, u, u.copy()
+
+
+def pin_gp_ratio_stop(o):
+    """Eq. (pgstop2): the gradient-projection phase stops at the first iterate
+    j >= 2 whose decrease is at most eta_1 times the largest earlier one.  The
+    phase is run independently here; the oracle's first phase (max_outer = 1)
+    must take as many iterates, with the paper's eta_1 = 0.1, eta_2 = 0.05 and
+    with eta_1 = 0.3, eta_2 = 0.01.  Every case stops by pgstop2, and with
+    eta_2 in place of eta_1 it would stop at another iterate."""
+    for seed in (0, 1, 4, 7, 8, 14):
+        A, b, l, u, x0 = _gp_case(seed)
+        csr = instances.dense_to_csr(A)
+        for eta1, eta2 in ((0.1, 0.05), (0.3, 0.01)):
+            want, decs, why, margin = _gp_phase(A, b, l, u, x0, eta1)
+            other = _gp_phase(A, b, l, u, x0, eta2)[0]
+            assert why == "pgstop2" and other != want, (seed, eta1, why, other)
+            assert margin > 1e-9, (seed, margin)
+            for j in range(1, want):
+                r = decs[j] / max(decs[:j])
+                assert abs(r - eta1) > 1e-6 * eta1, (seed, j, r)
+            st = o.gpcg(csr, b, l, u, x0, max_outer=1, eta1=eta1, eta2=eta2)[2]
+            assert st["gp_iters"] == want, (seed, eta1, st["gp_iters"], want)
+
+
+def pin_eta2_schedule(o):
+    """Eq. (cgstop3) and the reading of it: when the binding set equals the
+    active set after a projected search, CG runs again on that face with eta_2
+    multiplied by eta2_reduce; whenever a gradient-projection phase has run,
+    the next CG phase uses the initial eta_2 again.  Checked on the trace of
+    every CG phase (the eta its stopping test used, and its decreases, which
+    must meet eq. (cgstop1) with that eta) of solves with chains of face
+    repeats and with a gradient-projection phase after a repeat."""
+    cases = [(instances.obstacle(12, 0, amplitude=0.5, u_random=True), {}),
+             (instances.obstacle(16, 5, amplitude=0.5, u_random=True), dict(eta2=0.3)),
+             (instances.obstacle50(0), dict(eta2_reduce=0.5)),
+             (instances.obstacle50(0), {})]
+    after_repeat = 0
+    for inst, kw in cases:
+        opts = dict(TIGHT, **kw)
+        eta2 = kw.get("eta2", 0.05)
+        red = kw.get("eta2_reduce", 0.1)
+        _, _, st = o.solve_instance(inst, cg_trace_cap=400, dec_per=256, **opts)
+        tr = st["cg_phases_trace"]
+        assert st["status"] == 0 and len(tr) == st["cg_phases"]
+        assert tr[0]["repeat"] == 0
+        assert sum(t["repeat"] for t in tr) == st["face_repeats"] >= 2
+        for i, t in enumerate(tr):
+            if t["repeat"]:
+                assert t["eta"] == tr[i - 1]["eta"] * red, (inst.name, i, t["eta"])
+            else:
+                assert t["eta"] == eta2, (inst.name, i, t["eta"])
+                after_repeat += int(i > 0 and tr[i - 1]["repeat"] == 1)
+            if t["iters"] <= len(t["decs"]):
+                stop = _ratio_stop(t["decs"], t["eta"])
+                # the test fired at the last iteration, or never (rho = 0 / cap)
+                assert stop in (t["iters"], None), (inst.name, i, stop, t["iters"])
+    assert after_repeat >= 2
+
+
+def pin_objective(o):
+    """q(x) = 1/2 x'Ax - b'x (Section 2, sign of b as in g = Ax - b): the
+    oracle's objective against exact rational arithmetic on a tiny QP, and the
+    q its solves report against a sparse-library evaluation at the answer."""
+    inst = instances.tiny_dense(7, seed=31)
+    x = np.random.default_rng(8).standard_normal(7)
+    Af = [[Fraction(float(v)) for v in row] for row in inst.dense]
+    xf = [Fraction(float(v)) for v in x]
+    bf = [Fraction(float(v)) for v in inst.b]
+    qx = Fraction(1, 2) * sum(xf[i] * sum(Af[i][j] * xf[j] for j in range(7)) for i in range(7)) \
+        - sum(bf[i] * xf[i] for i in range(7))
+    got = o.objective(inst.csr(), inst.b, x)
+    assert abs(got - float(qx)) <= 1e-13 * (1.0 + abs(float(qx)))
+    for inst in (instances.obstacle50(3), instances.varcoef(48, 2)):
+        A = exact.csr_matrix(inst.csr())
+        x, _, st = o.solve_instance(inst)
+        want = 0.5 * x @ (A @ x) - inst.b @ x
+        assert abs(st["q"] - want) <= 1e-12 * (abs(want) + abs(inst.b @ x)), (inst.name, st["q"], want)
+
+
 # ---------------------------------------------------------------- whole method
 
 def pin_brute_force_tiny(o, count=40):
@@ -452,4 +655,8 @@ ALL_PINS = [
     pin_matches_independent_exact_solver,
     pin_invariants,
     pin_jacobi_gpcg_same_solution,
+    pin_cg_ratio_stop,
+    pin_gp_ratio_stop,
+    pin_eta2_schedule,
+    pin_objective,
 ]
