@@ -181,6 +181,31 @@ def _dptr(t) -> Optional[int]:
     return None if t is None else int(t.data_ptr())
 
 
+def _check_vec(t, n: int, dtypes, name: str, optional: bool = False):
+    """Raises ValueError unless t is a contiguous CUDA tensor of one of
+    `dtypes` with exactly n elements: the kernels index every array up to n
+    and would read or write out of bounds otherwise."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device, got {t.device}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(map(str, dtypes))}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+
+
+def _f64():
+    return (_torch().float64,)
+
+
 def _stream_ptr(stream=None) -> int:
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -222,8 +247,9 @@ class Operator:
     @staticmethod
     def stencil_var(nx: int, ny: int, wx, wy) -> "Operator":
         """wx: ny*(nx+1) FP64 device tensor; wy: (ny+1)*nx FP64 device tensor."""
-        assert wx.numel() == ny * (nx + 1) and wy.numel() == (ny + 1) * nx
         wx, wy = wx.contiguous(), wy.contiguous()
+        _check_vec(wx, ny * (nx + 1), _f64(), "wx")
+        _check_vec(wy, (ny + 1) * nx, _f64(), "wy")
         return Operator(gpcg_operator(kind=GPCG_OP_STENCIL5_VAR, nx=nx, ny=ny,
                                       wx=_dptr(wx), wy=_dptr(wy)), [wx, wy])
 
@@ -231,7 +257,11 @@ class Operator:
     def csr(rowptr, colind, vals) -> "Operator":
         """int32 rowptr (n+1), int32 colind (nnz), FP64 vals (nnz) on the device."""
         rowptr, colind, vals = rowptr.contiguous(), colind.contiguous(), vals.contiguous()
+        torch = _torch()
         n = rowptr.numel() - 1
+        _check_vec(rowptr, n + 1, (torch.int32,), "rowptr")
+        _check_vec(colind, colind.numel(), (torch.int32,), "colind")
+        _check_vec(vals, colind.numel(), _f64(), "vals")
         return Operator(gpcg_operator(kind=GPCG_OP_CSR, n=n, nnz=colind.numel(),
                                       rowptr=_dptr(rowptr), colind=_dptr(colind),
                                       vals=_dptr(vals)), [rowptr, colind, vals])
@@ -256,6 +286,10 @@ class Solver:
 
     def solve(self, b, l, u, x, g_out=None) -> dict:
         """x holds x0 on entry and the answer on return (FP64 device tensors)."""
+        n = self.op.n
+        for t, name in ((b, "b"), (l, "l"), (u, "u"), (x, "x")):
+            _check_vec(t, n, _f64(), name)
+        _check_vec(g_out, n, _f64(), "g_out", optional=True)
         st = gpcg_stats()
         rc = _lib.gpcg_solve(self.handle, _dptr(b), _dptr(l), _dptr(u), _dptr(x),
                              _dptr(g_out), C.byref(st))
@@ -265,17 +299,29 @@ class Solver:
     def autotune(self, b, l, u, x0, x_work=None) -> dict:
         """Times the launch configurations on this problem and keeps the
         fastest (gpcg_autotune); returns the report.  x0 is not modified."""
+        n = self.op.n
+        for t, name in ((b, "b"), (l, "l"), (u, "u"), (x0, "x0")):
+            _check_vec(t, n, _f64(), name)
         x = x_work if x_work is not None else _torch().empty_like(x0)
+        _check_vec(x, n, _f64(), "x_work")
         rep = gpcg_tune_report()
         check(_lib.gpcg_autotune(self.handle, _dptr(b), _dptr(l), _dptr(u), _dptr(x0),
                                  _dptr(x), C.byref(rep)), "gpcg_autotune")
         return rep.as_dict()
 
     def spmv(self, v, y, mask=None):
+        torch, n = _torch(), self.op.n
+        _check_vec(v, n, (torch.float64, torch.float32), "v")
+        _check_vec(y, n, (v.dtype,), "y")
+        _check_vec(mask, n, (torch.uint8,), "mask", optional=True)
         fn = _lib.gpcg_spmv_f32 if v.dtype.itemsize == 4 else _lib.gpcg_spmv
         check(fn(self.handle, _dptr(v), _dptr(y), _dptr(mask)), "gpcg_spmv")
 
     def projected_gradient(self, x, l, u, g, pg=None):
+        n = self.op.n
+        for t, name in ((x, "x"), (l, "l"), (u, "u"), (g, "g")):
+            _check_vec(t, n, _f64(), name)
+        _check_vec(pg, n, _f64(), "pg", optional=True)
         n2 = C.c_double()
         lo, up, nb = C.c_int64(), C.c_int64(), C.c_int64()
         check(_lib.gpcg_projected_gradient(self.handle, _dptr(x), _dptr(l), _dptr(u), _dptr(g),
@@ -314,10 +360,16 @@ class Batch:
     def solve(self, problems, mode=GPCG_BATCH_STEPPED):
         """problems: list of (b, l, u, x) device tensors; returns per-QP stats."""
         cnt = len(self.solvers)
+        if len(problems) != cnt:
+            raise ValueError(f"{cnt} problems expected, got {len(problems)}")
         probs = (gpcg_problem * cnt)()
         for i, p in enumerate(problems):
             b, l, u, x = p[:4]
             g = p[4] if len(p) > 4 else None
+            n = self.solvers[i].op.n
+            for t, name in ((b, "b"), (l, "l"), (u, "u"), (x, "x")):
+                _check_vec(t, n, _f64(), f"problems[{i}].{name}")
+            _check_vec(g, n, _f64(), f"problems[{i}].g_out", optional=True)
             probs[i] = gpcg_problem(_dptr(b), _dptr(l), _dptr(u), _dptr(x), _dptr(g))
         stats = (gpcg_stats * cnt)()
         check(_lib.gpcg_batch_solve(self.handle, probs, mode, stats), "gpcg_batch_solve")
@@ -327,9 +379,14 @@ class Batch:
         """Times the stepped-form launch configurations (gpcg_batch_autotune)
         and keeps the fastest; x0s are copied into the problems' x first."""
         cnt = len(self.solvers)
+        if len(problems) != cnt or len(x0s) != cnt:
+            raise ValueError(f"{cnt} problems and starts expected")
         probs = (gpcg_problem * cnt)()
         for i, p in enumerate(problems):
             b, l, u, x = p[:4]
+            n = self.solvers[i].op.n
+            for t, name in ((b, "b"), (l, "l"), (u, "u"), (x, "x"), (x0s[i], "x0")):
+                _check_vec(t, n, _f64(), f"problems[{i}].{name}")
             probs[i] = gpcg_problem(_dptr(b), _dptr(l), _dptr(u), _dptr(x), None)
         arr = (C.c_void_p * cnt)(*[_dptr(x) for x in x0s])
         rep = gpcg_tune_report()
@@ -385,6 +442,10 @@ class Server:
     def submit(self, tag: int, op: Operator, b, l, u, x0, x_out) -> int:
         """Queues a request; returns the C status (GPCG_ERR_NOSPACE if it can
         never fit).  The tensors are kept alive until completion."""
+        n = op.n
+        for t, name in ((b, "b"), (l, "l"), (u, "u"), (x0, "x0")):
+            _check_vec(t, n, _f64(), name)
+        _check_vec(x_out, n, _f64(), "x_out", optional=True)
         req = gpcg_request(op=op.desc, b=_dptr(b), l=_dptr(l), u=_dptr(u), x0=_dptr(x0),
                            x_out=_dptr(x_out), tag=tag)
         rc = _lib.gpcg_server_submit(self.handle, C.byref(req))

@@ -87,3 +87,54 @@ def test_free_set_forms_host_checks():
     opt = gpcg.default_options(free_set=gpcg.GPCG_FREESET_MATRIX, tile=512)
     rc = gpcg.gpcg_workspace_bytes(ctypes.byref(csr), ctypes.byref(opt), ctypes.byref(nbytes))
     assert rc == gpcg.GPCG_ERR_ARG
+
+
+def test_binding_rejects_bad_tensors_before_the_library():
+    """The binding checks device, dtype, contiguity and length of every array
+    before a pointer reaches the C ABI (a wrong one would make the kernels read
+    or write out of bounds)."""
+    import torch
+    import paper_cs_0101018_amd as gpcg
+    f64 = (torch.float64,)
+    with pytest.raises(ValueError, match="GPU"):
+        gpcg._check_vec(torch.zeros(10, dtype=torch.float64), 10, f64, "b")
+    with pytest.raises(ValueError, match="required"):
+        gpcg._check_vec(None, 10, f64, "x")
+    gpcg._check_vec(None, 10, f64, "g_out", optional=True)
+    with pytest.raises(ValueError, match="torch tensor"):
+        gpcg._check_vec([0.0] * 10, 10, f64, "l")
+
+
+class _FakeCudaTensor:
+    """Enough of a torch.Tensor's interface for the checks, on a 'cuda' device."""
+
+    def __init__(self, t, device="cuda"):
+        self._t = t
+        self.device = torch_device(device)
+        self.dtype = t.dtype
+
+    def is_contiguous(self):
+        return self._t.is_contiguous()
+
+    def numel(self):
+        return self._t.numel()
+
+
+def torch_device(s):
+    import torch
+    return torch.device(s)
+
+
+def test_binding_checks_dtype_contiguity_and_length(monkeypatch):
+    import torch
+    import paper_cs_0101018_amd as gpcg
+    monkeypatch.setattr(torch, "Tensor", _FakeCudaTensor)
+    f64 = (torch.float64,)
+    ok = _FakeCudaTensor(torch.zeros(12, dtype=torch.float64))
+    gpcg._check_vec(ok, 12, f64, "x")
+    with pytest.raises(ValueError, match="12 elements"):
+        gpcg._check_vec(_FakeCudaTensor(torch.zeros(11, dtype=torch.float64)), 12, f64, "x")
+    with pytest.raises(ValueError, match="dtype"):
+        gpcg._check_vec(_FakeCudaTensor(torch.zeros(12, dtype=torch.float32)), 12, f64, "x")
+    with pytest.raises(ValueError, match="contiguous"):
+        gpcg._check_vec(_FakeCudaTensor(torch.zeros(24, dtype=torch.float64)[::2]), 12, f64, "x")
