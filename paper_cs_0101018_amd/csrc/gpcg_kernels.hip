@@ -1030,7 +1030,12 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R, bool l
       else {
         const double beta = R[0] / d.gamma;
         const double pAp = R[1] - beta * R[0] / d.cg_alpha;  // p_{j+1}' A p_{j+1}
-        if (!(pAp > 0.0)) finish(d, GPCG_ERR_NOT_SPD);
+        // The recurrence can lose positivity by rounding once rho has nearly
+        // vanished (FP32 sums in the mixed form); w_j is then still a descent
+        // direction, so the CG phase ends with it.  Definiteness is checked
+        // directly elsewhere: z'Az at the set-up pass and d'Ad at every
+        // gradient-projection step.
+        if (!(pAp > 0.0)) start_ps(d);
         else {
           d.cg_beta = beta;
           d.cg_alpha = R[0] / pAp;
