@@ -263,6 +263,25 @@ int gpcg_projected_gradient(gpcg_handle h, const double *x, const double *l, con
                             const double *g, double *pg, double *norm2, int64_t *n_lower,
                             int64_t *n_upper, int64_t *n_nonbinding);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the result
+ * of gpcg_projected_gradient without a handle or workspace.  x, l, u, g: device
+ * FP64 arrays of length n; pg: NULL or a device FP64 array of length n;
+ * norm2 and the three counts: host outputs as in gpcg_projected_gradient (each
+ * may be NULL).  stream: hipStream_t as void* (NULL: default stream); the call
+ * waits for completion on it.  Its partial sums live in a fixed scratch array
+ * of the library, one per GPU (64 KiB + 32 B: four sums for each of at most
+ * 2048 workgroups, then the totals), held until the process ends; the call
+ * makes no device or host allocation.  n must be in [1, GPCG_NOALLOC_MAX_N]
+ * (GPCG_ERR_ARG otherwise).  The results are bitwise those of
+ * gpcg_projected_gradient.  Calls that overlap in time on one GPU (other
+ * threads, other streams) share that scratch array and race: serialise them. */
+#define GPCG_NOALLOC_MAX_N ((int64_t)1 << 34)
+int gpcg_projected_gradient_noalloc(int64_t n, const double *x, const double *l,
+                                    const double *u, const double *g, double *pg,
+                                    double *norm2, int64_t *n_lower, int64_t *n_upper,
+                                    int64_t *n_nonbinding, void *stream);
+
 /* --------------------------------------------------------------- autotuner
  * Picks the launch configuration of a handle by timing it: the launch form
  * (fused, split), the consecutive tiles per data workgroup of the split form

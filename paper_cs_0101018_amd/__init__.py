@@ -132,6 +132,9 @@ _SIGS = {
     "gpcg_spmv_f32": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gpcg_projected_gradient": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _P(C.c_double),
                                           _P(_i64), _P(_i64), _P(_i64)]),
+    "gpcg_projected_gradient_noalloc": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp,
+                                                  _P(C.c_double), _P(_i64), _P(_i64),
+                                                  _P(_i64), _vp]),
     "gpcg_batch_workspace_bytes": (C.c_int, [C.c_int, C.c_void_p, _P(_sz)]),
     "gpcg_batch_create": (C.c_int, [C.c_int, _P(_vp), _vp, _sz, _vp, _P(_vp)]),
     "gpcg_batch_solve": (C.c_int, [_vp, _P(gpcg_problem), C.c_int, _P(gpcg_stats)]),
@@ -404,6 +407,29 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+GPCG_NOALLOC_MAX_N = 1 << 34
+
+
+def projected_gradient_noalloc(x, l, u, g, pg=None, stream=None):
+    """gpcg_projected_gradient_noalloc: ||P grad q(x)||^2 and the face counts
+    of x without a handle or workspace (the library's fixed per-GPU scratch;
+    nothing is allocated).  Returns (norm2, n_lower, n_upper, n_nonbinding)."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        raise ValueError("x must be a torch tensor")
+    n = x.numel()
+    for t, name in ((x, "x"), (l, "l"), (u, "u"), (g, "g")):
+        _check_vec(t, n, _f64(), name)
+    _check_vec(pg, n, _f64(), "pg", optional=True)
+    n2 = C.c_double()
+    lo, up, nb = C.c_int64(), C.c_int64(), C.c_int64()
+    check(_lib.gpcg_projected_gradient_noalloc(n, _dptr(x), _dptr(l), _dptr(u), _dptr(g),
+                                               _dptr(pg), C.byref(n2), C.byref(lo),
+                                               C.byref(up), C.byref(nb), _stream_ptr(stream)),
+          "gpcg_projected_gradient_noalloc")
+    return n2.value, lo.value, up.value, nb.value
 
 
 def status_string(code: int) -> str:

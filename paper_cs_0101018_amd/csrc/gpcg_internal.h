@@ -20,6 +20,10 @@ namespace gpcg {
 
 constexpr int kBlock = 256;   // threads per workgroup (four wave64s)
 constexpr int kNP = 10;       // reduction slots per tile and pass
+// Projected-gradient building block: at most this many workgroups, each
+// leaving four partial sums, then the four totals.
+constexpr int kPgradMaxBlocks = 2048;
+constexpr int kPgradScratchDoubles = 4 * kPgradMaxBlocks + 4;
 
 enum Phase : int32_t {
   PH_INIT = 0,    // x <- mid(l, u, x0); g <- Ax - b; checks; P grad q norm; face counts
@@ -180,6 +184,12 @@ int gpcg_launch_spmv(const gpcg::QPDev *dqp, const gpcg::QPStatic *S, int64_t n,
                      void *y, const uint8_t *mask, int f32, int vec_nx, void *stream);
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
                       const double *g, double *pg, double *part, double *out4, void *stream);
+// The same on the library's own per-device scratch array (no workspace): *out4
+// receives the device address of the four totals.  0 on success; -1 no
+// current device, -2 the scratch address lookup failed, -3 a bad size or a
+// launch error.
+int gpcg_launch_pgrad_scratch(int64_t n, const double *x, const double *l, const double *u,
+                              const double *g, double *pg, const double **out4, void *stream);
 int gpcg_launch_convert_f32(const double *src, float *dst, int64_t count, void *stream);
 // 1 / diag(A) of the QP's operator into dinv (FP64 or FP32); the device state
 // must hold the operator.  Returns -1 on a launch error.

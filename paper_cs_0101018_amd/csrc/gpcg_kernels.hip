@@ -39,6 +39,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "gpcg.h"
 #include "gpcg_internal.h"
 
@@ -2117,12 +2119,69 @@ int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double 
                       const double *g, double *pg, double *part, double *out4, void *stream) {
   if (n <= 0) return -1;
   int grid = grid_for((n + kPgradUnroll - 1) / kPgradUnroll);
-  if (grid > 2048) grid = 2048;
+  if (grid > kPgradMaxBlocks) grid = kPgradMaxBlocks;
   hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x, l, u,
                      g, pg, part);
   hipLaunchKernelGGL(pgrad_final_kernel, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
                      part, out4);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Scratch of the allocation-free projected-gradient entry point: the partial
+// sums of at most kPgradMaxBlocks workgroups, then the four totals.  Every GPU
+// the library runs on holds its own copy until the process ends; calls on one
+// GPU share it (the last call's values stay).  Host code never passes the
+// array's name to a kernel: that is a host-side stand-in, not the device
+// address.  It uses the address hipGetSymbolAddress returns for the current
+// device, looked up once per device.
+static __device__ __align__(256) double scratch[kPgradScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];  // per device: the device address of `scratch`
+}  // namespace
+
+// The device address of this device's scratch array, looked up on the first
+// call with that device current; null on failure.
+static double *scratch_on_current_device(int *err) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *err = -1;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      *err = -2;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *err = 0;
+  return g_scratch_ptr[dev];
+}
+
+int gpcg_launch_pgrad_scratch(int64_t n, const double *x, const double *l, const double *u,
+                              const double *g, double *pg, const double **out4,
+                              void *stream) {
+  int err = 0;
+  double *base = scratch_on_current_device(&err);
+  if (!base) return err;
+  if (n <= 0) return -3;
+  int grid = grid_for((n + kPgradUnroll - 1) / kPgradUnroll);
+  if (grid > kPgradMaxBlocks) grid = kPgradMaxBlocks;
+  double *part = base;
+  double *tot = base + 4 * kPgradMaxBlocks;
+  // every slot the final kernel reads (4 per launched workgroup) is written by
+  // the first kernel: nothing needs clearing between calls
+  hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x, l, u,
+                     g, pg, part);
+  hipLaunchKernelGGL(pgrad_final_kernel, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
+                     (const double *)part, tot);
+  *out4 = tot;
+  return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 // 1 / diag(A): stencils from their weights (the same sums as the diagonal of

@@ -164,7 +164,7 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free
   };
   L.qp = take(sizeof(QPDev));
   L.slots = take(tile_slot_bytes(L.ntiles));  // at L.qp + kQPDevBytes
-  L.pgpart = take(sizeof(double) * 4 * 2048 + 64);
+  L.pgpart = take(sizeof(double) * kPgradScratchDoubles + 64);
   L.x1 = take(8 * (size_t)n);
   L.g0 = take(8 * (size_t)n);
   L.g1 = take(8 * (size_t)n);
@@ -956,12 +956,37 @@ int gpcg_projected_gradient(gpcg_handle h, const double *x, const double *l, con
                             int64_t *n_upper, int64_t *n_nonbinding) {
   if (!h || !x || !l || !u || !g) return fail(GPCG_ERR_ARG, "handle, x, l, u, g required");
   double *part = (double *)(h->ws + h->L.pgpart);
-  double *out4 = part + 4 * 2048;
+  double *out4 = part + 4 * kPgradMaxBlocks;
   if (gpcg_launch_pgrad(h->st.n, x, l, u, g, pg, part, out4, h->stream))
     return fail(GPCG_ERR_HIP, "projected-gradient launch failed");
   double r[4];
   HIP_OK(hipMemcpyAsync(r, out4, sizeof(r), hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
+  if (norm2) *norm2 = r[0];
+  if (n_lower) *n_lower = (int64_t)r[1];
+  if (n_upper) *n_upper = (int64_t)r[2];
+  if (n_nonbinding) *n_nonbinding = (int64_t)r[3];
+  return GPCG_OK;
+}
+
+int gpcg_projected_gradient_noalloc(int64_t n, const double *x, const double *l,
+                                    const double *u, const double *g, double *pg,
+                                    double *norm2, int64_t *n_lower, int64_t *n_upper,
+                                    int64_t *n_nonbinding, void *stream) {
+  if (!x || !l || !u || !g) return fail(GPCG_ERR_ARG, "x, l, u, g required");
+  if (n < 1 || n > GPCG_NOALLOC_MAX_N)
+    return fail(GPCG_ERR_ARG, "gpcg_projected_gradient_noalloc: n must be in [1, " +
+                                  std::to_string((long long)GPCG_NOALLOC_MAX_N) + "], got " +
+                                  std::to_string((long long)n));
+  const hipStream_t st = (hipStream_t)stream;
+  const double *tot = nullptr;
+  const int rc = gpcg_launch_pgrad_scratch(n, x, l, u, g, pg, &tot, st);
+  if (rc == -1) return fail(GPCG_ERR_HIP, "no current HIP device");
+  if (rc == -2) return fail(GPCG_ERR_HIP, "hipGetSymbolAddress of the scratch array failed");
+  if (rc) return fail(GPCG_ERR_HIP, "projected-gradient launch failed");
+  double r[4];
+  HIP_OK(hipMemcpyAsync(r, tot, sizeof(r), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
   if (norm2) *norm2 = r[0];
   if (n_lower) *n_lower = (int64_t)r[1];
   if (n_upper) *n_upper = (int64_t)r[2];

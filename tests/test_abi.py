@@ -138,3 +138,16 @@ def test_binding_checks_dtype_contiguity_and_length(monkeypatch):
         gpcg._check_vec(_FakeCudaTensor(torch.zeros(12, dtype=torch.float32)), 12, f64, "x")
     with pytest.raises(ValueError, match="contiguous"):
         gpcg._check_vec(_FakeCudaTensor(torch.zeros(24, dtype=torch.float64)[::2]), 12, f64, "x")
+
+
+def test_noalloc_size_limit_checked_on_host():
+    """The allocation-free entry point refuses sizes outside [1, GPCG_NOALLOC_MAX_N]
+    before any device work (the pointers below are never dereferenced)."""
+    import paper_cs_0101018_amd as gpcg
+    fake = ctypes.c_void_p(4096)
+    n2 = ctypes.c_double()
+    for n in (0, -5, gpcg.GPCG_NOALLOC_MAX_N + 1):
+        rc = gpcg.gpcg_projected_gradient_noalloc(n, fake, fake, fake, fake, None,
+                                                  ctypes.byref(n2), None, None, None, None)
+        assert rc == gpcg.GPCG_ERR_ARG
+        assert "n must be in" in gpcg.gpcg_last_error().decode()
