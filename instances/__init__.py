@@ -257,6 +257,13 @@ def batch512(seed: int = 0, count: int = 512, nmin: int = 32, nmax: int = 384):
     return [_mixed_member(c, nmin, nmax, i) for i, c in enumerate(children)]
 
 
+def batch_member(seed: int, index: int, count: int = 512, nmin: int = 32,
+                 nmax: int = 384) -> Instance:
+    """Member ``index`` of ``batch512(seed, count, nmin, nmax)`` alone."""
+    children = np.random.SeedSequence(seed).spawn(count)
+    return _mixed_member(children[index], nmin, nmax, index)
+
+
 def serve_trace(seed: int = 0, count: int = 4096, rate_hz: float = 200.0):
     """Poisson arrival times (seconds) for the serving workload."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 4]))

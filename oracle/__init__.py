@@ -70,7 +70,7 @@ def build(out: Optional[str] = None, mutant: int = 0) -> str:
     """Compile the oracle with gcc; returns the shared-library path."""
     out = out or LIB_PATH
     os.makedirs(os.path.dirname(out), exist_ok=True)
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-Wall", "-o", out + ".tmp", _SRC, "-lm"]
     if mutant:
         cmd.insert(1, f"-DORA_MUTANT={int(mutant)}")

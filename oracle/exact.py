@@ -157,3 +157,159 @@ def degenerate_set(x_star, g_star, l, u, rel: float = 1e-10):
     gmax = float(np.abs(g_star).max(initial=0.0))
     weak = act & (np.abs(g_star) <= rel * max(gmax, 1e-300))
     return near | weak
+
+
+# ----------------------------------------------------------------------------
+# Exact face solves for the constant five-point operator on a square grid.
+#
+# A = w (T (x) I + I (x) T), T = tridiag(-1, 2, -1) of order N (Dirichlet data
+# outside the grid), is diagonalised by the orthonormal type-I discrete sine
+# transform S along each axis: A = S Lam S with Lam_pq = w (4 - 2 cos(p pi h)
+# - 2 cos(q pi h)), h = 1 / (N + 1), p, q = 1..N.  Given a face -- the active
+# indices and the bound values there -- x* solves x_A = v, (A x - b)_F = 0.
+# With mu = (A x - b)_A (the multipliers, zero on F), A x = b + E mu, so
+# x = A^{-1} (b + E mu) and the conditions on A give the capacitance system
+#     C mu = v - E' A^{-1} b,   C = E' A^{-1} E  (m x m, SPD).
+# C_ab = sum_pq S_{i_a p} S_{j_a q} S_{i_b p} S_{j_b q} / Lam_pq.
+
+def _dst_eigs(N: int, w: float):
+    k = np.arange(1, N + 1)
+    lam1 = 2.0 - 2.0 * np.cos(k * np.pi / (N + 1))
+    return w * (lam1[:, None] + lam1[None, :])
+
+
+def poisson_solve(N: int, w: float, rhs):
+    """A^{-1} rhs for the constant five-point operator on an N x N grid (rows of
+    N unknowns, index j N + i), by the orthonormal DST-I."""
+    import scipy.fft
+    R = np.asarray(rhs, np.float64).reshape(N, N)
+    Y = scipy.fft.dstn(R, type=1, norm="ortho", workers=-1) / _dst_eigs(N, w)
+    return scipy.fft.idstn(Y, type=1, norm="ortho", workers=-1).ravel()
+
+
+def _green_block(N: int, w: float, idx):
+    """C = E' A^{-1} E for the grid indices idx (m x m), from the closed-form
+    eigenvectors S_{i p} = sqrt(2 h) sin(i' p pi h) (i' = i + 1)."""
+    idx = np.asarray(idx, np.int64)
+    m = len(idx)
+    h = 1.0 / (N + 1)
+    p = np.arange(1, N + 1)
+    i, j = idx % N, idx // N
+    si = np.sqrt(2 * h) * np.sin(np.outer(i + 1, p) * np.pi * h)  # m x N (column index)
+    sj = np.sqrt(2 * h) * np.sin(np.outer(j + 1, p) * np.pi * h)  # m x N (row index)
+    inv = 1.0 / _dst_eigs(N, w)                                   # [q (row), p (col)]
+    C = np.empty((m, m))
+    step = max(1, (1 << 27) // (N * N))  # rows of U per block: about 1 GB
+    for a0 in range(0, m, step):
+        a1 = min(m, a0 + step)
+        U = (sj[a0:a1, :, None] * si[a0:a1, None, :]).reshape(a1 - a0, N * N)
+        V = U * inv.ravel()[None, :]
+        for b0 in range(0, m, step):
+            b1 = min(m, b0 + step)
+            W = (sj[b0:b1, :, None] * si[b0:b1, None, :]).reshape(b1 - b0, N * N)
+            C[a0:a1, b0:b1] = V @ W.T
+    return 0.5 * (C + C.T)
+
+
+def face_solve_const(N: int, w: float, b, active_idx, active_val, refine: int = 2):
+    """x with x_A = active_val and (A x - b)_F = 0 for the constant five-point
+    operator (capacitance system above, then `refine` rounds of iterative
+    refinement on the free residual).  Returns (x, mu)."""
+    b = np.asarray(b, np.float64)
+    idx = np.asarray(active_idx, np.int64)
+    v = np.asarray(active_val, np.float64)
+    if len(idx) == 0:
+        return poisson_solve(N, w, b), np.zeros(0)
+    C = _green_block(N, w, idx)
+    Lc = np.linalg.cholesky(C)
+    csolve = lambda r: np.linalg.solve(Lc.T, np.linalg.solve(Lc, r))
+
+    def solve(rhs, vals):
+        y = poisson_solve(N, w, rhs)
+        mu = csolve(vals - y[idx])
+        e = np.zeros_like(rhs)
+        e[idx] = mu
+        return poisson_solve(N, w, rhs + e), mu
+
+    x, mu = solve(b, v)
+    x[idx] = v
+    A = stencil_const_csr(N, w)
+    for _ in range(refine):
+        r = b - A @ x
+        r[idx] = 0.0
+        dx, dmu = solve(r, np.zeros_like(v))
+        dx[idx] = 0.0
+        x += dx
+        mu += dmu
+    return x, mu
+
+
+def stencil_const_csr(N: int, w: float):
+    """The constant five-point operator as a SciPy CSR matrix."""
+    T = sp.diags([-np.ones(N - 1), 2.0 * np.ones(N), -np.ones(N - 1)], [-1, 0, 1])
+    I = sp.identity(N)
+    return (w * (sp.kron(I, T) + sp.kron(T, I))).tocsr()
+
+
+def xstar_from_face(N: int, w: float, b, l, u, lower_idx, upper_idx):
+    """x* of the QP with the constant five-point operator from a face
+    certificate (lower- and upper-active indices), verified: the result is
+    returned only if it satisfies the Kuhn-Tucker conditions -- then it is the
+    unique solution whatever produced the certificate.  Returns (x, g, kkt)."""
+    lower_idx = np.asarray(lower_idx, np.int64)
+    upper_idx = np.asarray(upper_idx, np.int64)
+    idx = np.concatenate([lower_idx, upper_idx])
+    val = np.concatenate([np.asarray(l)[lower_idx], np.asarray(u)[upper_idx]])
+    x, mu = face_solve_const(N, w, b, idx, val)
+    x = np.minimum(np.maximum(x, l), u)
+    A = stencil_const_csr(N, w)
+    g = A @ x - b
+    kkt = kkt_residual(A, b, l, u, x)
+    # rounding level of a residual entry: |b| + 8 w |x|, times a few ulps
+    scale = float(np.abs(b).max() + 8.0 * w * np.abs(x).max())
+    if not kkt <= 64 * np.finfo(float).eps * scale:
+        raise ValueError(f"face certificate does not give x*: KKT residual {kkt:.3e} "
+                         f"(rounding level {np.finfo(float).eps * scale:.3e})")
+    return x, g, kkt
+
+
+def pdas_const(N: int, w: float, b, l, u, x_init, max_iter: int = 50):
+    """The primal-dual active-set iteration of ``pdas`` with the face systems
+    of the constant five-point operator solved by ``face_solve_const`` (for
+    starts near x*, whose active sets are small).  Returns (x, iterations,
+    converged)."""
+    A = stencil_const_csr(N, w)
+    c = A.diagonal()
+    x = np.minimum(np.maximum(np.asarray(x_init, np.float64), l), u)
+    lam = A @ x - b
+    fixed = l == u
+    prevL = prevU = None
+    for it in range(1, max_iter + 1):
+        with np.errstate(invalid="ignore"):
+            Lset = fixed | (np.isfinite(l) & (lam + c * (l - x) > 0))
+            Uset = ~Lset & np.isfinite(u) & (lam + c * (u - x) < 0)
+        if prevL is not None and np.array_equal(Lset, prevL) and np.array_equal(Uset, prevU):
+            return x, it, True
+        prevL, prevU = Lset, Uset
+        lo, up = np.flatnonzero(Lset), np.flatnonzero(Uset)
+        x, _ = face_solve_const(N, w, b, np.concatenate([lo, up]),
+                                np.concatenate([l[lo], u[up]]))
+        lam = A @ x - b
+        lam[~(Lset | Uset)] = 0.0
+    return x, max_iter, False
+
+
+def read_face(path):
+    """(N, lower indices, upper indices) from a face certificate file: lines
+    'N <int>', 'lower <count>' then the indices, 'upper <count>' then the
+    indices; '#' starts a comment."""
+    toks = []
+    with open(path) as f:
+        for line in f:
+            toks += line.split("#", 1)[0].split()
+    it = iter(toks)
+    out = {}
+    for key in it:
+        cnt = int(next(it))
+        out[key] = cnt if key == "N" else np.array([int(next(it)) for _ in range(cnt)], np.int64)
+    return out["N"], out["lower"], out["upper"]

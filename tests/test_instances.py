@@ -23,3 +23,12 @@ def test_stencil_csr_sampled_rows_equal_full_assembly():
     assert B[others].nnz == 0
     v = rng.standard_normal(N * N)
     assert np.array_equal((B @ v)[rows], (A @ v)[rows])
+
+
+def test_batch_member_equals_batch_entry():
+    full = instances.batch512(0, count=16, nmin=8, nmax=24)
+    for i in (0, 7, 15):
+        one = instances.batch_member(0, i, count=16, nmin=8, nmax=24)
+        assert one.name == full[i].name and one.N == full[i].N
+        for k in ("b", "l", "u", "x0"):
+            assert np.array_equal(getattr(one, k), getattr(full[i], k))
