@@ -130,6 +130,23 @@ struct WgItem {
   int32_t tile0, ntile;
 };
 
+// What a CG iteration of a stencil QP reads besides the scalar state: the
+// operator and the CG vectors of one QP.  The kernels read it from the QP's
+// static state with uniform (scalar) loads before anything else, and issue
+// the CG operand loads from it before the state is known.  wx, wy and w are
+// those of the CG precision (FP32 copies in the mixed form).
+struct CGView {
+  int32_t op_kind, nx, ny, div_shift;
+  uint64_t div_magic;
+  int64_t n;
+  double w;
+  const void *wx, *wy;
+  void *rho[2], *uq[2], *sq[2];
+  void *pv, *wv;
+  const uint8_t *mask;
+  const void *dinv;  // Jacobi preconditioner or null
+};
+
 struct StepLaunch {
   QPDev *single;           // one QP: its state (tables unused)
   QPDev *const *qps;       // several QPs: device array of nqp pointers (transition kernel)

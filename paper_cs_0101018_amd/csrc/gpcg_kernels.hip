@@ -90,6 +90,17 @@ template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float
   return __fmaf_rn(a, b, c);
 }
 
+// Global-address-space view of a pointer: loads and stores through it are
+// global instructions.  Pointers read from memory (the state, the LDS copy of
+// it, the work items) are otherwise generic, and flat accesses also count
+// against the LDS counter, so every workgroup barrier waits for them.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(T *p) {
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------------ operator
 
 template <typename T>
@@ -130,8 +141,10 @@ template <typename T, class F>
 __device__ __forceinline__ T apply_row(const OpView<T> &A, int64_t k, F v) {
   if (A.kind == OPK_CSR) {
     T s = T(0);
-    const int32_t e0 = A.rowptr[k], e1 = A.rowptr[k + 1];
-    for (int32_t e = e0; e < e1; ++e) s = fmaT<T>(A.vals[e], v((int64_t)A.colind[e]), s);
+    const gptr<const int32_t> rp = gbl(A.rowptr), ci = gbl(A.colind);
+    const gptr<const T> va = gbl(A.vals);
+    const int32_t e0 = rp[k], e1 = rp[k + 1];
+    for (int32_t e = e0; e < e1; ++e) s = fmaT<T>(va[e], v((int64_t)ci[e]), s);
     return s;
   }
   const int32_t nx = A.nx;
@@ -145,7 +158,8 @@ __device__ __forceinline__ T apply_row(const OpView<T> &A, int64_t k, F v) {
   if (A.kind == OPK_CONST) return A.w * ((c - vW) + (c - vE) + ((c - vS) + (c - vN)));
   const int64_t ex = (int64_t)j * (nx + 1) + i;
   const int64_t ey = (int64_t)j * nx + i;
-  const T wW = A.wx[ex], wE = A.wx[ex + 1], wS = A.wy[ey], wN = A.wy[ey + nx];
+  const gptr<const T> gx = gbl(A.wx), gy = gbl(A.wy);
+  const T wW = gx[ex], wE = gx[ex + 1], wS = gy[ey], wN = gy[ey + nx];
   return (wW * (c - vW) + wE * (c - vE)) + (wS * (c - vS) + wN * (c - vN));
 }
 
@@ -159,10 +173,12 @@ template <class F>
 __device__ __forceinline__ Pair apply_row2(const OpView<double> &A, int64_t k, F v) {
   Pair r{0.0, 0.0};
   if (A.kind == OPK_CSR) {
-    const int32_t e0 = A.rowptr[k], e1 = A.rowptr[k + 1];
+    const gptr<const int32_t> rp = gbl(A.rowptr), ci = gbl(A.colind);
+    const gptr<const double> va = gbl(A.vals);
+    const int32_t e0 = rp[k], e1 = rp[k + 1];
     for (int32_t e = e0; e < e1; ++e) {
-      const Pair t = v((int64_t)A.colind[e]);
-      const double a = A.vals[e];
+      const Pair t = v((int64_t)ci[e]);
+      const double a = va[e];
       r.y = __fma_rn(a, t.y, r.y);
       r.s = __fma_rn(a, t.s, r.s);
     }
@@ -184,7 +200,8 @@ __device__ __forceinline__ Pair apply_row2(const OpView<double> &A, int64_t k, F
   }
   const int64_t ex = (int64_t)j * (nx + 1) + i;
   const int64_t ey = (int64_t)j * nx + i;
-  const double wW = A.wx[ex], wE = A.wx[ex + 1], wS = A.wy[ey], wN = A.wy[ey + nx];
+  const gptr<const double> gx = gbl(A.wx), gy = gbl(A.wy);
+  const double wW = gx[ex], wE = gx[ex + 1], wS = gy[ey], wN = gy[ey + nx];
   r.y = (wW * (c.y - W.y) + wE * (c.y - E.y)) + (wS * (c.y - So.y) + wN * (c.y - No.y));
   r.s = (wW * (c.s - W.s) + wE * (c.s - E.s)) + (wS * (c.s - So.s) + wN * (c.s - No.s));
   return r;
@@ -303,14 +320,16 @@ __device__ __forceinline__ void write_partial(double *slots, int par, int phase,
   const int ns = nslots(phase);
   block_slots(ns, f32, acc, accf);
   if (threadIdx.x == 0) {
-    for (int k = 0; k < ns; ++k) slots[slot_index(tile, par, k)] = acc[k];
+    const gptr<double> sl = gbl(slots);
+    for (int k = 0; k < ns; ++k) sl[slot_index(tile, par, k)] = acc[k];
   }
 }
 
 // Loads slot `tid` of parity par (always present) ahead of time.
 __device__ __forceinline__ void prefetch_slot(const double *slots, int par, double (&pf)[kNP]) {
+  const gptr<const double> sl = gbl(slots);
 #pragma unroll
-  for (int k = 0; k < kNP; ++k) pf[k] = slots[slot_index((int)threadIdx.x, par, k)];
+  for (int k = 0; k < kNP; ++k) pf[k] = sl[slot_index((int)threadIdx.x, par, k)];
 }
 
 // Adds slots t = tid + 256, tid + 512, ... (in that order) of parity par to
@@ -318,13 +337,14 @@ __device__ __forceinline__ void prefetch_slot(const double *slots, int par, doub
 template <int NS, int D = (NS <= 3 ? 8 : 2)>
 __device__ __forceinline__ void sum_slot_tail(const double *slots, int par, int ntiles,
                                               double (&res)[kNP], float (&vf)[2]) {
+  const gptr<const double> sl = gbl(slots);
   for (int base = (int)threadIdx.x + kBlock; base < ntiles; base += D * kBlock) {
     double buf[D][NS];
 #pragma unroll
     for (int u = 0; u < D; ++u) {
       const int t = base + u * kBlock;
 #pragma unroll
-      for (int k = 0; k < NS; ++k) buf[u][k] = t < ntiles ? slots[slot_index(t, par, k)] : 0.0;
+      for (int k = 0; k < NS; ++k) buf[u][k] = t < ntiles ? sl[slot_index(t, par, k)] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < D; ++u) {
@@ -478,11 +498,12 @@ __device__ __forceinline__ void grid_has(const QPStatic *S, int64_t p, int32_t &
 __device__ __forceinline__ void stencil_weights(const QPStatic *S, int64_t p, int32_t i,
                                                 int32_t j, double (&wt)[4]) {
   if (S->op_kind == OPK_VAR) {
+    const gptr<const double> wx = gbl(S->wx), wy = gbl(S->wy);
     const int64_t ex = (int64_t)j * (S->nx + 1) + i;
-    wt[0] = S->wx[ex];
-    wt[1] = S->wx[ex + 1];
-    wt[2] = S->wy[p];
-    wt[3] = S->wy[p + S->nx];
+    wt[0] = wx[ex];
+    wt[1] = wx[ex + 1];
+    wt[2] = wy[p];
+    wt[3] = wy[p + S->nx];
   }
 }
 
@@ -510,16 +531,17 @@ __device__ __forceinline__ void la_edge(int t, int &r, int &q) {
 __device__ __forceinline__ void la_load(const QPStatic *__restrict__ S, int cp, int64_t c0,
                                         LAOperands &O) {
   const int64_t n = S->n, nx = S->nx;
-  const double *__restrict__ x = S->x[cp];
-  const double *__restrict__ g = S->g[cp];
+  const gptr<const double> x = gbl((const double *)S->x[cp]);
+  const gptr<const double> g = gbl((const double *)S->g[cp]);
+  const gptr<const double> l = gbl(S->l), u = gbl(S->u), b = gbl(S->b);
   const int t = (int)threadIdx.x;
 #pragma unroll
   for (int r = -2; r <= 2; ++r) {
     const int64_t p = c0 + t + r * nx;
     const bool in = p >= 0 && p < n;
     O.x[r + 2] = in ? x[p] : 0.0;
-    O.l[r + 2] = in ? S->l[p] : 0.0;
-    O.u[r + 2] = in ? S->u[p] : 0.0;
+    O.l[r + 2] = in ? l[p] : 0.0;
+    O.u[r + 2] = in ? u[p] : 0.0;
     O.g[r + 2] = in ? g[p] : 0.0;
   }
   int er, eq;
@@ -527,8 +549,8 @@ __device__ __forceinline__ void la_load(const QPStatic *__restrict__ S, int cp, 
   const int64_t pe = c0 + eq + er * nx;
   const bool ine = t < 8 && pe >= 0 && pe < n;
   O.xe = ine ? x[pe] : 0.0;
-  O.le = ine ? S->l[pe] : 0.0;
-  O.ue = ine ? S->u[pe] : 0.0;
+  O.le = ine ? l[pe] : 0.0;
+  O.ue = ine ? u[pe] : 0.0;
   O.ge = ine ? g[pe] : 0.0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -538,7 +560,7 @@ __device__ __forceinline__ void la_load(const QPStatic *__restrict__ S, int cp, 
     if (in) grid_has(S, p, i, j, O.has[m]);
     else
       for (int e = 0; e < 4; ++e) O.has[m][e] = false;
-    O.b[m] = in ? S->b[p] : 0.0;
+    O.b[m] = in ? b[p] : 0.0;
     if (S->op_kind == OPK_VAR && in) stencil_weights(S, p, i, j, O.wt[m]);
     else
       for (int e = 0; e < 4; ++e) O.wt[m][e] = 0.0;
@@ -585,8 +607,8 @@ __device__ __forceinline__ void la_compute(const QPStatic *__restrict__ S, int c
         const double sk = s_s[1][t + 2];
         const double As = row5(S, O.wt[1], O.has[1], sk, s_s[1][t + 1], s_s[1][t + 3],
                                s_s[0][t + 2], s_s[2][t + 2]);
-        S->x[cp ^ 1][k] = yc;
-        S->g[cp ^ 1][k] = gy;
+        gbl(S->x[cp ^ 1])[k] = yc;
+        gbl(S->g[cp ^ 1])[k] = gy;
         face_acc(yc, yl, yu, gy, O.b[1], acc);
         acc[5] = __fma_rn(O.g[2], sk, acc[5]);
         acc[6] = __fma_rn(sk, As, acc[6]);
@@ -617,14 +639,14 @@ template <typename CT, bool PRE, bool LA, bool MAT>
 __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restrict__ slots,
                          const QPCore &d, int phase, int lpar, int64_t k0, int64_t k1,
                          double (&acc)[kNP], float (&accf)[2]) {
-  const double *__restrict__ l = S->l;
-  const double *__restrict__ u = S->u;
-  const double *__restrict__ b = S->b;
+  const gptr<const double> l = gbl(S->l);
+  const gptr<const double> u = gbl(S->u);
+  const gptr<const double> b = gbl(S->b);
   const int c = d.cur;
-  const double *__restrict__ x = S->x[c];
-  const double *__restrict__ g = S->g[c];
-  double *__restrict__ xn = S->x[c ^ 1];
-  double *__restrict__ gn = S->g[c ^ 1];
+  const gptr<const double> x = gbl((const double *)S->x[c]);
+  const gptr<const double> g = gbl((const double *)S->g[c]);
+  const gptr<double> xn = gbl(S->x[c ^ 1]);
+  const gptr<double> gn = gbl(S->g[c ^ 1]);
   constexpr int64_t st = kBlock;
   switch (phase) {
     case PH_INIT: {
@@ -632,8 +654,8 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       // before or after its owner projects it: mid(l, u, .) is idempotent, so
       // both give the same value (l <= u is verified by this same pass).
       const OpView<double> A = op_view<double>(S);
-      double *x0 = S->x[0];
-      double *__restrict__ g0 = S->g[0];
+      const gptr<double> x0 = gbl(S->x[0]);
+      const gptr<double> g0 = gbl(S->g[0]);
       auto xv = [&](int64_t j) { return mid3(l[j], u[j], x0[j]); };
       for (int64_t k = k0 + threadIdx.x; k < k1; k += st) {
         const double xo = x0[k], lk = l[k], uk = u[k], bk = b[k];
@@ -687,21 +709,21 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
     } break;
     case PH_CG_INIT: {
       const OpView<CT> A = op_view<CT>(S);
-      uint8_t *__restrict__ mask = S->mask;
+      const gptr<uint8_t> mask = gbl(S->mask);
       // the first CG iteration runs in the next launch, which reads parity
       // lpar ^ 1 (in the list form two launches later, in the matrix form
       // four: parity lpar)
       const int fp = S->list ? lpar : lpar ^ 1;
-      CT *__restrict__ r0 = (CT *)S->rho[fp];
-      CT *__restrict__ u0 = (CT *)S->uq[fp];
-      CT *__restrict__ r1 = (CT *)S->rho[fp ^ 1];
-      CT *__restrict__ u1 = (CT *)S->uq[fp ^ 1];
-      CT *__restrict__ s0 = (CT *)S->sq[0];
-      CT *__restrict__ s1 = (CT *)S->sq[1];
-      CT *__restrict__ p = (CT *)S->pv;
-      CT *__restrict__ w = (CT *)S->wv;
+      const gptr<CT> r0 = gbl((CT *)S->rho[fp]);
+      const gptr<CT> u0 = gbl((CT *)S->uq[fp]);
+      const gptr<CT> r1 = gbl((CT *)S->rho[fp ^ 1]);
+      const gptr<CT> u1 = gbl((CT *)S->uq[fp ^ 1]);
+      const gptr<CT> s0 = gbl((CT *)S->sq[0]);
+      const gptr<CT> s1 = gbl((CT *)S->sq[1]);
+      const gptr<CT> p = gbl((CT *)S->pv);
+      const gptr<CT> w = gbl((CT *)S->wv);
       // preconditioned residual z = D^-1 rho (rho itself without a preconditioner)
-      const CT *__restrict__ dinv = PRE ? (const CT *)S->dinv : nullptr;
+      const gptr<const CT> dinv = gbl(PRE ? (const CT *)S->dinv : nullptr);
       auto zv = [&](int64_t j) {
         const double xj = x[j];
         const CT r = (l[j] < xj && xj < u[j]) ? (CT)(-g[j]) : CT(0);
@@ -775,30 +797,30 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
       break;
     case PH_CG_ITER: {
       const OpView<CT> A = op_view<CT>(S);
-      const uint8_t *__restrict__ mask = S->mask;
+      const gptr<const uint8_t> mask = gbl((const uint8_t *)S->mask);
       const int par = lpar;  // CG buffers alternate with the launch parity
       const bool first = d.first != 0;
       const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
-      const CT *__restrict__ ro = (const CT *)S->rho[par];
-      const CT *__restrict__ uo = (const CT *)S->uq[par];
-      const CT *__restrict__ so = (const CT *)S->sq[par];
-      CT *__restrict__ rn = (CT *)S->rho[par ^ 1];
-      CT *__restrict__ un = (CT *)S->uq[par ^ 1];
-      CT *__restrict__ sn = (CT *)S->sq[par ^ 1];
-      CT *__restrict__ p = (CT *)S->pv;
-      CT *__restrict__ w = (CT *)S->wv;
+      const gptr<const CT> ro = gbl((const CT *)S->rho[par]);
+      const gptr<const CT> uo = gbl((const CT *)S->uq[par]);
+      const gptr<const CT> so = gbl((const CT *)S->sq[par]);
+      const gptr<CT> rn = gbl((CT *)S->rho[par ^ 1]);
+      const gptr<CT> un = gbl((CT *)S->uq[par ^ 1]);
+      const gptr<CT> sn = gbl((CT *)S->sq[par ^ 1]);
+      const gptr<CT> p = gbl((CT *)S->pv);
+      const gptr<CT> w = gbl((CT *)S->wv);
       // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i
       auto snew = [&](int64_t j) { return first ? uo[j] : fmaT<CT>(be, so[j], uo[j]); };
       auto rnew = [&](int64_t j) { return fmaT<CT>(-al, snew(j), ro[j]); };
       // z = D^-1 rho with the Jacobi preconditioner, else rho; u = A z
-      const CT *__restrict__ dinv = PRE ? (const CT *)S->dinv : nullptr;
+      const gptr<const CT> dinv = gbl(PRE ? (const CT *)S->dinv : nullptr);
       auto znew = [&](int64_t j) {
         const CT r = rnew(j);
         return dinv ? r * dinv[j] : r;
       };
       CT gam = CT(0), del = CT(0);
-      const int32_t *__restrict__ list = S->list;
-      const int32_t *__restrict__ mrow = S->mrow;
+      const gptr<const int32_t> list = gbl((const int32_t *)S->list);
+      const gptr<const int32_t> mrow = gbl((const int32_t *)S->mrow);
       // list form: entries [k0, k1) of the free list; mask form: rows [k0, k1)
       const int64_t e1 = list ? (k1 < d.m_free ? k1 : d.m_free) : k1;
       for (int64_t e = k0 + threadIdx.x; e < e1; e += st) {
@@ -818,9 +840,10 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
         rn[k] = r1;
         CT u1;
         if (MAT && mrow) {  // A_F: the free columns only (the others hold z = 0)
-          const CT *__restrict__ mv = (const CT *)S->mval;
+          const gptr<const CT> mv = gbl((const CT *)S->mval);
+          const gptr<const int32_t> mc = gbl((const int32_t *)S->mcol);
           u1 = CT(0);
-          for (int32_t q = mrow[e]; q < mrow[e + 1]; ++q) u1 = fmaT<CT>(mv[q], znew(S->mcol[q]), u1);
+          for (int32_t q = mrow[e]; q < mrow[e + 1]; ++q) u1 = fmaT<CT>(mv[q], znew(mc[q]), u1);
         } else {
           u1 = apply_row<CT>(A, k, znew);
         }
@@ -838,8 +861,8 @@ __device__ void run_pass(const QPStatic *__restrict__ S, const double *__restric
     } break;
     case PH_PS_TRIAL: {
       const OpView<double> A = op_view<double>(S);
-      const uint8_t *__restrict__ mask = S->mask;
-      const CT *__restrict__ w = (const CT *)S->wv;
+      const gptr<const uint8_t> mask = gbl((const uint8_t *)S->mask);
+      const gptr<const CT> w = gbl((const CT *)S->wv);
       const double a = d.alpha;
       // the CG direction is zero on A(x_k): those entries do not move
       auto yv = [&](int64_t j) {
@@ -1120,9 +1143,50 @@ __device__ __forceinline__ void copy_dyn(const QPDyn *src, QPDyn *dst) {
         reinterpret_cast<const uint32_t *>(src)[threadIdx.x];
 }
 
+// The LDS state into its global copy (global stores).
+__device__ __forceinline__ void store_dyn(const QPDyn *lds, QPDyn *dst) {
+  if (threadIdx.x < kDynWords)
+    gbl(reinterpret_cast<uint32_t *>(dst))[threadIdx.x] =
+        reinterpret_cast<const uint32_t *>(lds)[threadIdx.x];
+}
+
 // ------------------------------------------------------------------ kernels
 
 // ------------------------------------------- speculative CG operand loads
+
+// Element c (0 or 1) of a two-entry array held in registers, without a
+// dynamic index (which would place the array in scratch memory).
+template <typename T>
+__device__ __forceinline__ T pick2(T const (&a)[2], int c) {
+  return c ? a[1] : a[0];
+}
+
+
+// The CG view of a QP read from its static state (global memory or the LDS
+// copy): the pointers of the CG precision CT.
+template <typename CT>
+__device__ __forceinline__ CGView make_cg_view(const QPStatic *S) {
+  CGView V;
+  V.op_kind = S->op_kind;
+  V.nx = S->nx;
+  V.ny = S->ny;
+  V.div_shift = S->div_shift;
+  V.div_magic = S->div_magic;
+  V.n = S->n;
+  V.w = sizeof(CT) == 4 ? (double)S->w32 : S->w;
+  V.wx = sizeof(CT) == 4 ? (const void *)S->wx32 : (const void *)S->wx;
+  V.wy = sizeof(CT) == 4 ? (const void *)S->wy32 : (const void *)S->wy;
+  for (int c = 0; c < 2; ++c) {
+    V.rho[c] = S->rho[c];
+    V.uq[c] = S->uq[c];
+    V.sq[c] = S->sq[c];
+  }
+  V.pv = S->pv;
+  V.wv = S->wv;
+  V.mask = S->mask;
+  V.dinv = S->dinv;
+  return V;
+}
 
 // Operands of one CG iteration at unknown k of a stencil operator.  They
 // depend only on k and on the launch parity (the CG buffers alternate with
@@ -1143,27 +1207,29 @@ struct CGOperands {
 // Loads the operands of one CG iteration at unknown k of a tile of kBlock
 // consecutive unknowns.  The west and east neighbours are the neighbouring
 // threads of the tile (exchanged through LDS after the update); only the
-// first and last threads load the row outside the tile.
+// first and last threads load the row outside the tile.  Every access is a
+// global (not flat) load: it counts only against the vector memory counter,
+// so the loads stay in flight across the workgroup barriers that wait for
+// LDS traffic.
 template <typename CT, bool PRE>
-__device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t k,
+__device__ __forceinline__ void cg_prefetch(const CGView &V, int lpar, int64_t k,
                                             CGOperands<CT> &P) {
-  const OpView<CT> A = op_view<CT>(S);
-  const CT *__restrict__ ro = (const CT *)S->rho[lpar];
-  const CT *__restrict__ uo = (const CT *)S->uq[lpar];
-  const CT *__restrict__ so = (const CT *)S->sq[lpar];
-  P.m = S->mask[k];
+  const gptr<const CT> ro = gbl((const CT *)pick2(V.rho, lpar));
+  const gptr<const CT> uo = gbl((const CT *)pick2(V.uq, lpar));
+  const gptr<const CT> so = gbl((const CT *)pick2(V.sq, lpar));
+  P.m = gbl(V.mask)[k];
   P.r = ro[k];
   P.u = uo[k];
   P.s = so[k];
-  P.p = ((const CT *)S->pv)[k];
-  P.w = ((const CT *)S->wv)[k];
-  const int32_t nx = A.nx;
-  const int32_t j = (int32_t)(((uint64_t)k * A.magic) >> A.shift);
+  P.p = gbl((const CT *)V.pv)[k];
+  P.w = gbl((const CT *)V.wv)[k];
+  const int32_t nx = V.nx;
+  const int32_t j = (int32_t)(((uint64_t)k * V.div_magic) >> V.div_shift);
   const int32_t i = (int32_t)(k - (int64_t)j * nx);
   P.hasW = i > 0;
   P.hasE = i < nx - 1;
   P.hasS = j > 0;
-  P.hasN = j < A.ny - 1;
+  P.hasN = j < V.ny - 1;
   P.rS = P.hasS ? ro[k - nx] : CT(0);
   P.uS = P.hasS ? uo[k - nx] : CT(0);
   P.sS = P.hasS ? so[k - nx] : CT(0);
@@ -1176,19 +1242,21 @@ __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t
   P.rX = kx >= 0 ? ro[kx] : CT(0);
   P.uX = kx >= 0 ? uo[kx] : CT(0);
   P.sX = kx >= 0 ? so[kx] : CT(0);
-  const CT *__restrict__ dinv = PRE ? (const CT *)S->dinv : nullptr;
-  if (dinv) {
+  if (PRE && V.dinv) {
+    const gptr<const CT> dinv = gbl((const CT *)V.dinv);
     P.dk = dinv[k];
     P.dS = P.hasS ? dinv[k - nx] : CT(0);
     P.dN = P.hasN ? dinv[k + nx] : CT(0);
     P.dX = kx >= 0 ? dinv[kx] : CT(0);
   }
-  if (A.kind == OPK_VAR) {
+  if (V.op_kind == OPK_VAR) {
+    const gptr<const CT> wx = gbl((const CT *)V.wx);
+    const gptr<const CT> wy = gbl((const CT *)V.wy);
     const int64_t ex = (int64_t)j * (nx + 1) + i;
-    P.wt[0] = A.wx[ex];
-    P.wt[1] = A.wx[ex + 1];
-    P.wt[2] = A.wy[k];
-    P.wt[3] = A.wy[k + nx];
+    P.wt[0] = wx[ex];
+    P.wt[1] = wx[ex + 1];
+    P.wt[2] = wy[k];
+    P.wt[3] = wy[k + nx];
   }
 }
 
@@ -1198,12 +1266,12 @@ __device__ __forceinline__ void cg_prefetch(const QPStatic *S, int lpar, int64_t
 // west and east neighbours from LDS; the formulas and their order are those
 // of the generic path, so the results are bitwise equal to it.
 template <typename CT, bool PRE>
-__device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCore &d, int lpar,
+__device__ __forceinline__ void cg_iter_prefetched(const CGView &V, const QPCore &d, int lpar,
                                                    int64_t k, bool own, const CGOperands<CT> &P,
                                                    CT &gam, CT &del) {
   __shared__ CT s_z1[kBlock];
   const bool first = d.first != 0;
-  const bool pre = PRE && S->dinv != nullptr;
+  const bool pre = PRE && V.dinv != nullptr;
   const CT al = (CT)d.cg_alpha, be = (CT)d.cg_beta;
   // s_i = u_i + beta s_{i-1} (= A p_i);  rho_{i+1} = rho_i - alpha s_i;
   // z = D^-1 rho with the Jacobi preconditioner, else rho; u = A z
@@ -1227,19 +1295,19 @@ __device__ __forceinline__ void cg_iter_prefetched(const QPStatic *S, const QPCo
   if (!own || !P.m) return;
   const CT zk = pre ? P.r * P.dk : P.r;
   const CT pk = first ? zk : fmaT<CT>(be, P.p, zk);
-  ((CT *)S->wv)[k] = fmaT<CT>(al, pk, P.w);
-  ((CT *)S->pv)[k] = pk;
-  ((CT *)S->sq[lpar ^ 1])[k] = sk;
-  ((CT *)S->rho[lpar ^ 1])[k] = r1;
+  gbl((CT *)V.wv)[k] = fmaT<CT>(al, pk, P.w);
+  gbl((CT *)V.pv)[k] = pk;
+  gbl((CT *)pick2(V.sq, lpar ^ 1))[k] = sk;
+  gbl((CT *)pick2(V.rho, lpar ^ 1))[k] = r1;
   CT u1;
-  if (S->op_kind == OPK_CONST) {
-    const OpView<CT> A = op_view<CT>(S);
-    u1 = A.w * ((z1 - v[0]) + (z1 - v[1]) + ((z1 - v[2]) + (z1 - v[3])));
+  if (V.op_kind == OPK_CONST) {
+    const CT w = (CT)V.w;
+    u1 = w * ((z1 - v[0]) + (z1 - v[1]) + ((z1 - v[2]) + (z1 - v[3])));
   } else {
     u1 = (P.wt[0] * (z1 - v[0]) + P.wt[1] * (z1 - v[1])) +
          (P.wt[2] * (z1 - v[2]) + P.wt[3] * (z1 - v[3]));
   }
-  ((CT *)S->uq[lpar ^ 1])[k] = u1;
+  gbl((CT *)pick2(V.uq, lpar ^ 1))[k] = u1;
   gam = fmaT<CT>(r1, z1, gam);
   del = fmaT<CT>(z1, u1, del);
 }
@@ -1265,23 +1333,25 @@ __device__ __forceinline__ void gp_prefetch(const QPStatic *S, int cp, int64_t k
   G.has[2] = j > 0;
   G.has[3] = j < S->ny - 1;
   const int64_t nb[5] = {k, k - 1, k + 1, k - nx, k + nx};
-  const double *__restrict__ x = S->x[cp];
-  const double *__restrict__ g = S->g[cp];
+  const gptr<const double> x = gbl((const double *)S->x[cp]);
+  const gptr<const double> g = gbl((const double *)S->g[cp]);
+  const gptr<const double> l = gbl(S->l), u = gbl(S->u);
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     const bool in = q == 0 || G.has[q - 1];
     G.x[q] = in ? x[nb[q]] : 0.0;
-    G.l[q] = in ? S->l[nb[q]] : 0.0;
-    G.u[q] = in ? S->u[nb[q]] : 0.0;
+    G.l[q] = in ? l[nb[q]] : 0.0;
+    G.u[q] = in ? u[nb[q]] : 0.0;
     G.g[q] = in ? g[nb[q]] : 0.0;
   }
-  G.b = S->b[k];
+  G.b = gbl(S->b)[k];
   if (S->op_kind == OPK_VAR) {
+    const gptr<const double> wx = gbl(S->wx), wy = gbl(S->wy);
     const int64_t ex = (int64_t)j * (nx + 1) + i;
-    G.wt[0] = S->wx[ex];
-    G.wt[1] = S->wx[ex + 1];
-    G.wt[2] = S->wy[k];
-    G.wt[3] = S->wy[k + nx];
+    G.wt[0] = wx[ex];
+    G.wt[1] = wx[ex + 1];
+    G.wt[2] = wy[k];
+    G.wt[3] = wy[k + nx];
   }
 }
 
@@ -1313,8 +1383,8 @@ __device__ __forceinline__ void gp_pass_prefetched(const QPStatic *S, const QPCo
   const double As = row5(S, G.wt, G.has, sv[0], sv[1], sv[2], sv[3], sv[4]);
   const double xk = G.x[0], lk = G.l[0], uk = G.u[0], gk = G.g[0], bk = G.b;
   const double gy = Ay - bk;
-  S->x[d.cur ^ 1][k] = y[0];
-  S->g[d.cur ^ 1][k] = gy;
+  gbl(S->x[d.cur ^ 1])[k] = y[0];
+  gbl(S->g[d.cur ^ 1])[k] = gy;
   face_acc(y[0], lk, uk, gy, bk, acc);
   acc[5] = __fma_rn(gk, sv[0], acc[5]);
   acc[6] = __fma_rn(sv[0], As, acc[6]);
@@ -1344,18 +1414,28 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   }
   const int par = L.parity;
   double *slots = tile_slots(q);
-  // the state first (everything waits for the pass it names), then the
-  // slots and the early CG operands
-  copy_dyn(&q->dyn[par], &sd);
-  copy_static(&q->st, &ss);
+  // Every load that does not depend on the state is issued first, together:
+  // this thread's word of the state and of the static part (clamped to a
+  // word inside the struct; only the threads that own a word store it), the
+  // slots of tile tid, and the early CG operands; the LDS copies are written
+  // once they arrive.
+  const int tid = (int)threadIdx.x;
+  const int sw = tid - (kBlock - kStaticWords);
+  const uint32_t dyn_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par]))
+      [tid < kDynWords ? tid : kDynWords - 1];
+  const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
   double pf[kNP];
   prefetch_slot(slots, par, pf);
   const uint64_t clk = wall_clock64();
-  // SPEC launches hold only stencil QPs with one unknown per thread
+  // SPEC launches hold only stencil QPs with one unknown per thread; the CG
+  // view is read from the state with uniform (scalar) loads
   const int64_t kk = (int64_t)tile * kBlock + threadIdx.x;
-  const bool own = SPEC && kk < q->st.n;
+  const CGView V = make_cg_view<CT>(&q->st);
+  const bool own = SPEC && kk < V.n;
   CGOperands<CT> P{};
-  if (own) cg_prefetch<CT, PRE>(&q->st, par, kk, P);
+  if (own) cg_prefetch<CT, PRE>(V, par, kk, P);
+  if (tid < kDynWords) reinterpret_cast<uint32_t *>(&sd)[tid] = dyn_w;
+  if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
   __syncthreads();
   const QPStatic *S = &ss;
   const int ntiles = S->ntiles, mixed = S->mixed;
@@ -1385,7 +1465,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   const int phase = sd.c.phase;
   // the next launch's state: written now (the pass below only reads it)
   if (tile == 0) {
-    copy_dyn(&sd, &q->dyn[par ^ 1]);
+    store_dyn(&sd, &q->dyn[par ^ 1]);
     if (threadIdx.x == 0 && s_fresh_done && S->host_flag)
       __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
@@ -1398,7 +1478,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
     if (SPEC && phase == PH_CG_ITER) {
       CT gam = CT(0), del = CT(0);
-      cg_iter_prefetched<CT, PRE>(S, sd.c, par, kk, own, P, gam, del);
+      cg_iter_prefetched<CT, PRE>(V, sd.c, par, kk, own, P, gam, del);
       if (sizeof(CT) == 4) {
         accf[0] = (float)gam;
         accf[1] = (float)del;
@@ -1429,11 +1509,16 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ QPStatic ss;
   __shared__ int s_fresh_done;
-  QPDev *q = L.single ? L.single : L.qps[blockIdx.x];
+  QPDev *q = L.single ? L.single : gbl(L.qps)[blockIdx.x];
   const int par = L.parity;
   const double *slots = tile_slots(q);
-  copy_dyn(&q->dyn[par], &sd);  // the state first: everything waits for it
-  copy_static(&q->st, &ss);
+  // the state words, the static words and the slots are loaded together; the
+  // LDS copies are written once they arrive
+  const int tid = (int)threadIdx.x;
+  const int sw = tid - (kBlock - kStaticWords);
+  const uint32_t dyn_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par]))
+      [tid < kDynWords ? tid : kDynWords - 1];
+  const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
   double pf[kNP];
   prefetch_slot(slots, par, pf);
   // one QP (its tile count is a launch argument): the two slots a CG pass
@@ -1443,13 +1528,16 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   const int nt = L.single ? L.total_tiles : 0;
   const bool early = nt > kBlock && nt <= (kEarly + 1) * kBlock;
   double e0[kEarly], e1[kEarly];
+  const gptr<const double> sl = gbl(slots);
 #pragma unroll
   for (int m = 0; m < kEarly; ++m) {
     const int t = (int)threadIdx.x + (m + 1) * kBlock;
-    e0[m] = (early && t < nt) ? slots[slot_index(t, par, 0)] : 0.0;
-    e1[m] = (early && t < nt) ? slots[slot_index(t, par, 1)] : 0.0;
+    e0[m] = (early && t < nt) ? sl[slot_index(t, par, 0)] : 0.0;
+    e1[m] = (early && t < nt) ? sl[slot_index(t, par, 1)] : 0.0;
   }
   const uint64_t clk = wall_clock64();
+  if (tid < kDynWords) reinterpret_cast<uint32_t *>(&sd)[tid] = dyn_w;
+  if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
   __syncthreads();
   const QPStatic *S = &ss;
   if (sd.c.pending) {
@@ -1487,7 +1575,7 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
     sd.c.pending = sd.c.phase == PH_DONE ? 0 : 1;
   }
   __syncthreads();
-  copy_dyn(&sd, &q->dyn[par ^ 1]);
+  store_dyn(&sd, &q->dyn[par ^ 1]);
   if (threadIdx.x == 0 && s_fresh_done && S->host_flag) {
     __threadfence();
     __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1508,7 +1596,7 @@ static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 constexpr int kPartAll = 0, kPartCG = 1, kPartRest = 2;
 
 template <typename CT, bool SPEC, bool PRE, int PART = kPartAll, bool MAT = false>
-__global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
+__global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
   __shared__ QPStatic ss;
   const int wg = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -1525,14 +1613,22 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
     nt = it.ntile;
   }
   const int par = L.parity;
+  // the state words and the early CG operands are loaded together; the LDS
+  // copies are written once they arrive
+  const int tid = (int)threadIdx.x;
+  const int sw = tid - (kBlock - kStaticWords);
+  const uint32_t core_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c))
+      [tid < kCoreWords ? tid : kCoreWords - 1];
+  const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
   int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
-  bool own = kk < q->st.n;
+  // the CG view, read from the state before anything is stored (uniform:
+  // scalar loads)
+  const CGView V = make_cg_view<CT>(&q->st);
+  bool own = kk < V.n;
   CGOperands<CT> P{};
-  if (SPEC && own) cg_prefetch<CT, PRE>(&q->st, par, kk, P);
-  if (threadIdx.x < kCoreWords)
-    reinterpret_cast<uint32_t *>(&sc)[threadIdx.x] =
-        reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c)[threadIdx.x];
-  copy_static(&q->st, &ss);
+  if (SPEC && own) cg_prefetch<CT, PRE>(V, par, kk, P);
+  if (tid < kCoreWords) reinterpret_cast<uint32_t *>(&sc)[tid] = core_w;
+  if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
   __syncthreads();
   const QPStatic *S = &ss;
   const int phase = sc.phase;
@@ -1554,9 +1650,9 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(StepLaunch L) {
         if (!SPEC || tile != t0 || c != 0) {
           kk = (int64_t)tile * S->tile + (int64_t)c * kBlock + threadIdx.x;
           own = kk < S->n;
-          if (own) cg_prefetch<CT, PRE>(S, par, kk, P);
+          if (own) cg_prefetch<CT, PRE>(V, par, kk, P);
         }
-        cg_iter_prefetched<CT, PRE>(S, sc, par, kk, own, P, gam, del);
+        cg_iter_prefetched<CT, PRE>(V, sc, par, kk, own, P, gam, del);
       }
       double acc[kNP];
       float accf[2] = {(float)gam, (float)del};
