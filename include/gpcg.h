@@ -303,7 +303,10 @@ typedef struct {
   int32_t prefetch;     /* 1: CG operands loaded before the state is read    */
   int32_t chunk;        /* passes per graph replay                           */
   int32_t shrink;       /* stepped batch: the launch is re-formed over the
-                           unfinished QPs once 1/shrink of its tiles are done */
+                           unfinished QPs once 1/shrink of its tiles are done;
+                           0: the queue form (one launch table for the whole
+                           solve; every pass, a device-side queue holds the
+                           work items of the QPs that are not done) */
   int32_t cg_kernel;    /* split form, 1: CG iterations in a data kernel of
                            their own (see gpcg_options.cg_kernel)            */
   double ms;            /* wall time of one solve                            */
@@ -386,7 +389,8 @@ typedef struct {
   uint64_t tag;
   int32_t status;
   gpcg_stats stats;
-  double t_submit, t_admit, t_done; /* host clock, seconds                */
+  double t_submit, t_admit, t_done; /* host clock, seconds; t_done: when the
+                                       answer was seen copied to x_out     */
 } gpcg_completion;
 
 /* Arena bytes one request of this operator needs at this precision. */
@@ -395,9 +399,13 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
 /* Queues a request (arrays must stay valid until it is admitted; x_out until
  * it completes).  GPCG_ERR_NOSPACE if it can never fit the arena. */
 int gpcg_server_submit(gpcg_server s, const gpcg_request *req);
-/* Admits what fits, runs one quantum of device passes over every resident
- * request, retires finished requests.  *active receives the number of
- * requests still queued or resident. */
+/* One turn of the serving loop, without waiting for the stream except to
+ * keep at most two quanta in flight: requests whose device done word is set
+ * have the copies of their answers (to x_out) and final states queued;
+ * requests whose copies have passed complete (their slot and arena space are
+ * free again); queued requests are admitted while a slot and arena space are
+ * free; one quantum of device passes over every running request is queued.
+ * *active receives the number of requests queued, running or completing. */
 int gpcg_server_step(gpcg_server s, int *active);
 /* Moves up to max finished completions into out; *got receives the count. */
 int gpcg_server_poll(gpcg_server s, gpcg_completion *out, int max, int *got);

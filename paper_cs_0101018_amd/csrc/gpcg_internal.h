@@ -156,7 +156,16 @@ struct StepLaunch {
   int32_t parity;          // this launch reads dyn/partials[parity]
   int32_t tiles_per_wg;    // one QP, split form: consecutive tiles per data workgroup
   int32_t data_grid;       // split form: workgroups of the data kernel
-  int32_t pad;
+  int32_t item_tiles;      // queue form: tiles per queued work item
+  // Queue form (several QPs, split form): the transition kernel of launch
+  // parity p appends the work items of every QP that is not done to
+  // queue[p * queue_cap ...], counting them in qcount[p] (and zeroes the
+  // other parity's count); the data kernel runs the qcount[p] queued items
+  // with a fixed grid.  No work item exists for a finished QP.
+  int32_t queue_cap;       // items per parity
+  int32_t pad2;
+  WgItem *queue;           // 2 * queue_cap items, or null (item table / one QP)
+  int32_t *qcount;         // 2 counters
 };
 
 struct PersistLaunch {
@@ -181,6 +190,9 @@ constexpr int kVarCgk = 4;
 // kVarMat: some QP of the launch has the matrix free set (the kernels that
 // carry its count and fill passes; never with kVarSpec).
 constexpr int kVarMat = 8;
+// kVarQueue: the data kernels of the queue form (a fixed grid running the
+// items the transition kernel queued; never with kVarSpec).
+constexpr int kVarQueue = 16;
 
 }  // namespace gpcg
 
@@ -207,6 +219,10 @@ int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double 
 // launch error.
 int gpcg_launch_pgrad_scratch(int64_t n, const double *x, const double *l, const double *u,
                               const double *g, double *pg, const double **out4, void *stream);
+// Copies `bytes` (a multiple of 8, both ends 8-byte aligned) from src
+// (device memory or mapped coherent host memory) to dst with a kernel.
+// Returns -1 on a bad argument or launch error.
+int gpcg_launch_copy(void *dst, const void *src, size_t bytes, void *stream);
 int gpcg_launch_convert_f32(const double *src, float *dst, int64_t count, void *stream);
 // 1 / diag(A) of the QP's operator into dinv (FP64 or FP32); the device state
 // must hold the operator.  Returns -1 on a launch error.

@@ -1119,6 +1119,14 @@ __device__ __forceinline__ void advance(const QPStatic *S, QPDyn &sd, const doub
   sd.t_last = now;
 }
 
+// The word a QP's solve leaves in its mapped host flag when it is done:
+// nonzero, with the copy of x that holds the answer (bit 1) and the parity
+// of the state copy that holds the final state (bit 2), so that the host can
+// fetch both without waiting for the stream.
+__device__ __forceinline__ int32_t done_word(int cur, int final_parity) {
+  return 1 | (cur << 1) | (final_parity << 2);
+}
+
 // --------------------------------------------------------- state transfer
 
 // The read-only part of a QP's state is copied into LDS with the dynamic
@@ -1467,7 +1475,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   if (tile == 0) {
     store_dyn(&sd, &q->dyn[par ^ 1]);
     if (threadIdx.x == 0 && s_fresh_done && S->host_flag)
-      __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(S->host_flag, done_word(sd.c.cur, par ^ 1), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
   }
   if (phase != PH_DONE) {
     const int64_t k0 = (int64_t)tile * S->tile;
@@ -1508,9 +1517,13 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
 __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   __shared__ QPDyn sd;
   __shared__ QPStatic ss;
-  __shared__ int s_fresh_done;
-  QPDev *q = L.single ? L.single : gbl(L.qps)[blockIdx.x];
+  __shared__ int s_fresh_done, s_base;
   const int par = L.parity;
+  // queue form: the next transition appends to the other parity's queue,
+  // which the data kernel before this one has finished reading
+  if (L.queue && blockIdx.x == 0 && threadIdx.x == 0) L.qcount[par ^ 1] = 0;
+  QPDev *q = L.single ? L.single : gbl(L.qps)[blockIdx.x];
+  if (!q) return;  // an empty slot of the server's table
   const double *slots = tile_slots(q);
   // the state words, the static words and the slots are loaded together; the
   // LDS copies are written once they arrive
@@ -1578,7 +1591,27 @@ __global__ __launch_bounds__(kBlock) void transition_kernel(StepLaunch L) {
   store_dyn(&sd, &q->dyn[par ^ 1]);
   if (threadIdx.x == 0 && s_fresh_done && S->host_flag) {
     __threadfence();
-    __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(S->host_flag, done_word(sd.c.cur, par ^ 1), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (L.queue && sd.c.phase != PH_DONE) {
+    // queue form: this QP's work items for the data kernel of this launch
+    const int T = L.item_tiles;
+    const int ntiles = S->ntiles;
+    const int nitems = (ntiles + T - 1) / T;
+    if (threadIdx.x == 0) s_base = atomicAdd(&L.qcount[par], nitems);
+    __syncthreads();
+    WgItem *queue = L.queue + (int64_t)par * L.queue_cap;
+    for (int i = tid; i < nitems; i += kBlock) {
+      const int at = s_base + i;
+      if (at < L.queue_cap) {
+        WgItem it;
+        it.q = q;
+        it.tile0 = i * T;
+        it.ntile = ntiles - i * T < T ? ntiles - i * T : T;
+        queue[at] = it;
+      }
+    }
   }
 }
 
@@ -1595,42 +1628,13 @@ static_assert(sizeof(QPCore) % 4 == 0 && kCoreWords <= kBlock, "QPCore copy");
 // workgroups stay in flight); kPartRest every pass but those.
 constexpr int kPartAll = 0, kPartCG = 1, kPartRest = 2;
 
-template <typename CT, bool SPEC, bool PRE, int PART = kPartAll, bool MAT = false>
-__global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
-  __shared__ QPCore sc;
-  __shared__ QPStatic ss;
-  const int wg = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  QPDev *q;
-  int t0, nt;
-  if (L.single) {
-    q = L.single;
-    t0 = wg * L.tiles_per_wg;
-    nt = L.tiles_per_wg;  // clipped to the QP's tiles below
-  } else {
-    const WgItem it = L.items[wg];
-    q = it.q;
-    t0 = it.tile0;
-    nt = it.ntile;
-  }
-  const int par = L.parity;
-  // the state words and the early CG operands are loaded together; the LDS
-  // copies are written once they arrive
-  const int tid = (int)threadIdx.x;
-  const int sw = tid - (kBlock - kStaticWords);
-  const uint32_t core_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c))
-      [tid < kCoreWords ? tid : kCoreWords - 1];
-  const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
-  int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
-  // the CG view, read from the state before anything is stored (uniform:
-  // scalar loads)
-  const CGView V = make_cg_view<CT>(&q->st);
-  bool own = kk < V.n;
-  CGOperands<CT> P{};
-  if (SPEC && own) cg_prefetch<CT, PRE>(V, par, kk, P);
-  if (tid < kCoreWords) reinterpret_cast<uint32_t *>(&sc)[tid] = core_w;
-  if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
-  __syncthreads();
-  const QPStatic *S = &ss;
+// The pass of one work item (tiles [t0, t0 + nt) of QP q, clipped to its
+// tiles) with its state in LDS (sc, S) and its CG view V.  With SPEC the
+// operands of the first chunk are in P already (own: its unknown exists).
+template <typename CT, bool SPEC, bool PRE, int PART, bool MAT>
+__device__ __forceinline__ void pass_item(QPDev *q, int par, int t0, int nt, const QPCore &sc,
+                                          const QPStatic *S, const CGView &V, int64_t kk,
+                                          bool own, CGOperands<CT> &P) {
   const int phase = sc.phase;
   if (phase == PH_DONE) return;
   const int mixed = S->mixed, ntiles = S->ntiles;
@@ -1646,7 +1650,20 @@ __global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
     const int nchunk = S->tile / kBlock;
     for (int tile = t0; tile < t1; ++tile) {
       CT gam = CT(0), del = CT(0);
-      for (int c = 0; c < nchunk; ++c) {
+      int c = 0;
+      if (nchunk == 2 && (!SPEC || tile != t0)) {
+        // two chunks: the operands of both are loaded before either is
+        // used (twice the loads in flight), then the chunks run in order
+        const int64_t ka = (int64_t)tile * S->tile + threadIdx.x, kb = ka + kBlock;
+        const bool owna = ka < S->n, ownb = kb < S->n;
+        CGOperands<CT> Q{};
+        if (owna) cg_prefetch<CT, PRE>(V, par, ka, P);
+        if (ownb) cg_prefetch<CT, PRE>(V, par, kb, Q);
+        cg_iter_prefetched<CT, PRE>(V, sc, par, ka, owna, P, gam, del);
+        cg_iter_prefetched<CT, PRE>(V, sc, par, kb, ownb, Q, gam, del);
+        c = 2;
+      }
+      for (; c < nchunk; ++c) {
         if (!SPEC || tile != t0 || c != 0) {
           kk = (int64_t)tile * S->tile + (int64_t)c * kBlock + threadIdx.x;
           own = kk < S->n;
@@ -1678,6 +1695,65 @@ __global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
     run_pass<CT, PRE, false, MAT>(S, slots, sc, phase, par, k0, k1, acc, accf);
     write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
     if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
+  }
+}
+
+template <typename CT, bool SPEC, bool PRE, int PART = kPartAll, bool MAT = false,
+          bool QUEUE = false>
+__global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
+  __shared__ QPCore sc;
+  __shared__ QPStatic ss;
+  const int wg = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int par = L.parity;
+  const int tid = (int)threadIdx.x;
+  const int sw = tid - (kBlock - kStaticWords);
+  if constexpr (QUEUE) {
+    // queue form: one workgroup per queued item (the grid covers the
+    // largest possible queue; workgroups beyond the count return at once).
+    // Items are dealt to the XCDs in contiguous runs over the count, so the
+    // neighbouring tiles of a QP share an L2.
+    const int count = L.qcount[par];
+    if ((int)blockIdx.x >= count) return;
+    const WgItem it = (L.queue + (int64_t)par * L.queue_cap)[xcd_tile((int)blockIdx.x, count)];
+    QPDev *q = it.q;
+    const uint32_t core_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c))
+        [tid < kCoreWords ? tid : kCoreWords - 1];
+    const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
+    const CGView V = make_cg_view<CT>(&q->st);
+    CGOperands<CT> P{};
+    if (tid < kCoreWords) reinterpret_cast<uint32_t *>(&sc)[tid] = core_w;
+    if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
+    __syncthreads();
+    pass_item<CT, false, PRE, PART, MAT>(q, par, it.tile0, it.ntile, sc, &ss, V, 0, false, P);
+  } else {
+  QPDev *q;
+  int t0, nt;
+  if (L.single) {
+    q = L.single;
+    t0 = wg * L.tiles_per_wg;
+    nt = L.tiles_per_wg;  // clipped to the QP's tiles below
+  } else {
+    const WgItem it = L.items[wg];
+    q = it.q;
+    t0 = it.tile0;
+    nt = it.ntile;
+  }
+  // the state words and the early CG operands are loaded together; the LDS
+  // copies are written once they arrive
+  const uint32_t core_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par ^ 1].c))
+      [tid < kCoreWords ? tid : kCoreWords - 1];
+  const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
+  const int64_t kk = (int64_t)t0 * kBlock + threadIdx.x;
+  // the CG view, read from the state before anything is stored (uniform:
+  // scalar loads)
+  const CGView V = make_cg_view<CT>(&q->st);
+  const bool own = kk < V.n;
+  CGOperands<CT> P{};
+  if (SPEC && own) cg_prefetch<CT, PRE>(V, par, kk, P);
+  if (tid < kCoreWords) reinterpret_cast<uint32_t *>(&sc)[tid] = core_w;
+  if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
+  __syncthreads();
+  pass_item<CT, SPEC, PRE, PART, MAT>(q, par, t0, nt, sc, &ss, V, kk, own, P);
   }
 }
 
@@ -1769,7 +1845,8 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistLaunch P) {
     __syncthreads();
     if (threadIdx.x == 0 && S->host_flag) {
       __threadfence();
-      __hip_atomic_store(S->host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(S->host_flag, done_word(sd.c.cur, 0), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -2078,30 +2155,36 @@ int gpcg_launch_persistent(const PersistLaunch &P, int grid, int mixed, void *st
 
 void *gpcg_transition_kernel_ptr() { return (void *)&transition_kernel; }
 
-template <int PART>
-static void *pass_ptr(int mixed, int variant) {
-  const bool sp = variant & kVarSpec, pr = variant & kVarPre;
+template <int PART, bool QUEUE>
+static void *pass_ptr_q(int mixed, int variant) {
+  const bool sp = !QUEUE && (variant & kVarSpec), pr = variant & kVarPre;
   if constexpr (PART != kPartCG) {
     if (variant & kVarMat) {
       if (mixed)
-        return pr ? (void *)&pass_kernel<float, false, true, PART, true>
-                  : (void *)&pass_kernel<float, false, false, PART, true>;
-      return pr ? (void *)&pass_kernel<double, false, true, PART, true>
-                : (void *)&pass_kernel<double, false, false, PART, true>;
+        return pr ? (void *)&pass_kernel<float, false, true, PART, true, QUEUE>
+                  : (void *)&pass_kernel<float, false, false, PART, true, QUEUE>;
+      return pr ? (void *)&pass_kernel<double, false, true, PART, true, QUEUE>
+                : (void *)&pass_kernel<double, false, false, PART, true, QUEUE>;
     }
   }
   if (mixed) {
     if (sp)
-      return pr ? (void *)&pass_kernel<float, true, true, PART>
-                : (void *)&pass_kernel<float, true, false, PART>;
-    return pr ? (void *)&pass_kernel<float, false, true, PART>
-              : (void *)&pass_kernel<float, false, false, PART>;
+      return pr ? (void *)&pass_kernel<float, true, true, PART, false, QUEUE>
+                : (void *)&pass_kernel<float, true, false, PART, false, QUEUE>;
+    return pr ? (void *)&pass_kernel<float, false, true, PART, false, QUEUE>
+              : (void *)&pass_kernel<float, false, false, PART, false, QUEUE>;
   }
   if (sp)
-    return pr ? (void *)&pass_kernel<double, true, true, PART>
-              : (void *)&pass_kernel<double, true, false, PART>;
-  return pr ? (void *)&pass_kernel<double, false, true, PART>
-            : (void *)&pass_kernel<double, false, false, PART>;
+    return pr ? (void *)&pass_kernel<double, true, true, PART, false, QUEUE>
+              : (void *)&pass_kernel<double, true, false, PART, false, QUEUE>;
+  return pr ? (void *)&pass_kernel<double, false, true, PART, false, QUEUE>
+            : (void *)&pass_kernel<double, false, false, PART, false, QUEUE>;
+}
+
+template <int PART>
+static void *pass_ptr(int mixed, int variant) {
+  return (variant & kVarQueue) ? pass_ptr_q<PART, true>(mixed, variant)
+                               : pass_ptr_q<PART, false>(mixed, variant);
 }
 
 void *gpcg_pass_kernel_ptr(int mixed, int variant) {
@@ -2112,11 +2195,11 @@ void *gpcg_pass_kernel_ptr(int mixed, int variant) {
 // The kernel of the passes the CG kernel skips: the early CG loads are of no
 // use there.
 void *gpcg_rest_kernel_ptr(int mixed, int variant) {
-  return pass_ptr<kPartRest>(mixed, variant & (kVarPre | kVarMat));
+  return pass_ptr<kPartRest>(mixed, variant & (kVarPre | kVarMat | kVarQueue));
 }
 
 int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {
-  if (L.data_grid < 1 || (!L.single && (!L.qps || !L.items || L.nqp < 1))) return -1;
+  if (L.data_grid < 1 || (!L.single && (!L.qps || (!L.items && !L.queue) || L.nqp < 1))) return -1;
   const int tgrid = L.single ? 1 : L.nqp;
   hipLaunchKernelGGL(transition_kernel, dim3(tgrid), dim3(kBlock), 0, (hipStream_t)stream, L);
   hipLaunchKernelGGL(reinterpret_cast<void (*)(StepLaunch)>(gpcg_pass_kernel_ptr(mixed, spec)),
@@ -2313,6 +2396,32 @@ int gpcg_launch_diag_inv(const QPDev *dqp, void *dinv, int f32, void *stream) {
   else
     hipLaunchKernelGGL(diag_inv_kernel<double>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
                        dqp, (double *)dinv);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// 8-byte words from src to dst: device memory, or mapped coherent host
+// memory on the source side.  The library moves every piece of state and
+// every table its kernels read with this kernel rather than with a copy
+// engine: a later launch then sees the new contents however the lines were
+// cached before (on this GPU, data that a DMA copy writes over lines a
+// kernel has read has been seen stale by later kernels).
+__global__ __launch_bounds__(kBlock) void copy_words_kernel(const uint64_t *src, uint64_t *dst,
+                                                            int64_t words) {
+  const gptr<const uint64_t> s = gbl(src);
+  const gptr<uint64_t> d = gbl(dst);
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < words;
+       k += (int64_t)gridDim.x * kBlock)
+    d[k] = s[k];
+}
+
+int gpcg_launch_copy(void *dst, const void *src, size_t bytes, void *stream) {
+  if (bytes == 0) return 0;
+  if (bytes % 8 || (uintptr_t)dst % 8 || (uintptr_t)src % 8) return -1;
+  const int64_t words = (int64_t)(bytes / 8);
+  int64_t grid = (words + kBlock - 1) / kBlock;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)grid), dim3(kBlock), 0,
+                     (hipStream_t)stream, (const uint64_t *)src, (uint64_t *)dst, words);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

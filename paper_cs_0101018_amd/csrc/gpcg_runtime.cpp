@@ -221,6 +221,24 @@ int alloc_flag(PinnedWords *f, size_t words) {
   return GPCG_OK;
 }
 
+// Pinned host memory that kernels read directly (mapped, coherent): the
+// staging of state and tables, moved to the device by gpcg_launch_copy.
+int alloc_pinned(void **host, void **dev, size_t bytes) {
+  *host = nullptr;
+  *dev = nullptr;
+  HIP_OK(hipHostMalloc(host, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(*host, 0, bytes);
+  HIP_OK(hipHostGetDevicePointer(dev, *host, 0));
+  return GPCG_OK;
+}
+
+// A device copy by kernel (see gpcg_launch_copy).
+#define COPY_OK(dst, src, bytes, stream)                                         \
+  do {                                                                           \
+    if (gpcg_launch_copy((dst), (src), (bytes), (stream)) != 0)                  \
+      return fail(GPCG_ERR_HIP, "device copy failed (" #dst ")");               \
+  } while (0)
+
 double wall_clock_hz() {
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1e8;
@@ -480,7 +498,9 @@ struct LaunchCfg {
   int tiles_per_wg;  // split form: consecutive tiles per data workgroup
   int spec;          // CG operands loaded before the state is known (stencils)
   int chunk;         // passes per graph replay / host check (even)
-  int shrink = 3;    // stepped batch: re-form the launch once 1/shrink of its tiles are done
+  int shrink = 3;    // stepped batch: re-form the launch once 1/shrink of its tiles are done;
+                     // 0: the queue form (never re-formed; a device queue holds the
+                     // work items of the QPs that are not done)
   int cgk = 0;       // split form: CG iterations in a data kernel of their own
   bool operator==(const LaunchCfg &o) const {
     return split == o.split && tiles_per_wg == o.tiles_per_wg && spec == o.spec &&
@@ -516,6 +536,7 @@ struct gpcg_handle_s {
   QPStatic st;          // static part (x[0] filled per solve)
   QPDev *dqp;           // device state
   QPDev *stage;         // pinned host staging for uploads / downloads
+  QPDev *stage_dev;     // its device address
   PinnedWords flag;     // DONE flag written by the device
   hipGraphExec_t graph = nullptr;
   LaunchCfg graph_cfg{};  // configuration the graph was built for
@@ -599,7 +620,7 @@ int upload_solve(gpcg_handle_s *h, const double *b, const double *l, const doubl
                    : 0;
   initial_dyn(q.dyn[0]);
   initial_dyn(q.dyn[1]);
-  HIP_OK(hipMemcpyAsync(h->dqp, &q, sizeof(QPDev), hipMemcpyHostToDevice, stream));
+  COPY_OK(h->dqp, h->stage_dev, sizeof(QPDev), stream);
   return GPCG_OK;
 }
 
@@ -611,9 +632,8 @@ int finish_solve(gpcg_handle_s *h, int final_parity, double *g_out, hipStream_t 
   const QPCore &d = h->stage->dyn[final_parity].c;
   const QPStatic &s = h->stage->st;
   const size_t bytes = sizeof(double) * (size_t)s.n;
-  if (d.cur == 1)
-    HIP_OK(hipMemcpyAsync(s.x[0], s.x[1], bytes, hipMemcpyDeviceToDevice, stream));
-  if (g_out) HIP_OK(hipMemcpyAsync(g_out, s.g[d.cur], bytes, hipMemcpyDeviceToDevice, stream));
+  if (d.cur == 1) COPY_OK(s.x[0], s.x[1], bytes, stream);
+  if (g_out) COPY_OK(g_out, s.g[d.cur], bytes, stream);
   HIP_OK(hipStreamSynchronize(stream));
   return GPCG_OK;
 }
@@ -699,10 +719,11 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   };
   rc = alloc_flag(&h->flag, 16);
   if (rc) return cleanup(rc);
-  void *st = nullptr;
-  if (hipHostMalloc(&st, sizeof(QPDev), hipHostMallocDefault) != hipSuccess)
-    return cleanup(fail(GPCG_ERR_HIP, "hipHostMalloc of the staging state failed"));
+  void *st = nullptr, *st_dev = nullptr;
+  rc = alloc_pinned(&st, &st_dev, sizeof(QPDev));
+  if (rc) return cleanup(rc);
   h->stage = (QPDev *)st;
+  h->stage_dev = (QPDev *)st_dev;
   fill_static(h);
   h->cfg.split = o.form == GPCG_FORM_SPLIT ||
                  (o.form == GPCG_FORM_AUTO && h->st.n > (int64_t)kFusedMaxTiles * kBlock);
@@ -735,8 +756,7 @@ int gpcg_create(const gpcg_operator *op, const gpcg_options *opt, void *workspac
   // the operator part of the device state is valid from here on (the
   // building-block kernels read it; solves rewrite only the vector pointers)
   h->stage->st = h->st;
-  if (hipMemcpyAsync(&h->dqp->st, &h->stage->st, sizeof(QPStatic), hipMemcpyHostToDevice,
-                     h->stream) != hipSuccess)
+  if (gpcg_launch_copy(&h->dqp->st, &h->stage_dev->st, sizeof(QPStatic), h->stream) != 0)
     return cleanup(fail(GPCG_ERR_HIP, "state upload failed in create"));
   // Jacobi preconditioner: 1 / diag(A) from the operator in the device state
   if (L.dinv && gpcg_launch_diag_inv(h->dqp, h->ws + L.dinv, h->st.mixed, h->stream) != 0)
@@ -815,8 +835,7 @@ int timed_solve(gpcg_handle h, const LaunchCfg &c, const double *b, const double
   double best = 1e300;
   int rc = GPCG_OK;
   for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
-    if (hipMemcpyAsync(x, x0, sizeof(double) * (size_t)h->st.n, hipMemcpyDeviceToDevice,
-                       h->stream) != hipSuccess ||
+    if (gpcg_launch_copy(x, x0, sizeof(double) * (size_t)h->st.n, h->stream) != 0 ||
         hipStreamSynchronize(h->stream) != hipSuccess) {
       rc = fail(GPCG_ERR_HIP, "copy of x0 failed in autotune");
       break;
@@ -1034,6 +1053,11 @@ size_t items_offset(int count) {
   return align_up(sizeof(void *) * (size_t)count) + align_up(sizeof(int32_t) * (count + 1));
 }
 
+// The device work queue of the queue form, after the tables: two counters,
+// then two arrays (one per launch parity) of `items` work items.
+size_t queue_bytes(size_t items) { return kAlign + align_up(sizeof(WgItem) * 2 * items); }
+
+
 // Work items of a split data kernel over the QPs qp[0..cnt): runs of at most
 // T consecutive tiles, QP by QP.  Returns the number of items.
 int fill_items(WgItem *out, QPDev *const *qp, const int32_t *ntiles, int cnt, int T) {
@@ -1096,6 +1120,10 @@ struct gpcg_batch_s {
   int32_t *prefix;     // device
   WgItem *items;       // device
   size_t tbytes;
+  char *stage_dev;     // device address of the pinned tables (kBlock more: zeros)
+  int32_t *qcount;     // device: the queue form's two counters
+  WgItem *queue;       // device: 2 x queue_cap items
+  size_t queue_cap;
   char *stage;         // pinned copy of the tables
   PinnedWords flags;   // one DONE word per QP
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1117,7 +1145,8 @@ int gpcg_batch_workspace_bytes(int count, const gpcg_handle *handles, size_t *by
   if (count < 1 || !bytes || !handles) return fail(GPCG_ERR_ARG, "count >= 1 and handles required");
   for (int i = 0; i < count; ++i)
     if (!handles[i]) return fail(GPCG_ERR_ARG, "NULL handle in batch");
-  *bytes = tables_bytes(count, batch_items(count, handles));
+  const size_t items = batch_items(count, handles);
+  *bytes = tables_bytes(count, items) + queue_bytes(items);
   return GPCG_OK;
 }
 
@@ -1130,8 +1159,10 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
     if (handles[i]->st.mixed != handles[0]->st.mixed)
       return fail(GPCG_ERR_ARG, "all handles of a batch must share the precision");
   }
-  const size_t need = tables_bytes(count, batch_items(count, handles));
-  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < need)
+  const size_t nitems = batch_items(count, handles);
+  const size_t need = tables_bytes(count, nitems);
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 ||
+      ws_bytes < need + queue_bytes(nitems))
     return fail(GPCG_ERR_WORKSPACE, "batch workspace missing, misaligned or too small");
   auto *b = new gpcg_batch_s();
   b->hs.assign(handles, handles + count);
@@ -1142,12 +1173,15 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
   b->prefix = (int32_t *)(b->ws + align_up(sizeof(void *) * (size_t)count));
   b->items = (WgItem *)(b->ws + items_offset(count));
   b->tbytes = need;
+  b->qcount = (int32_t *)(b->ws + align_up(need));
+  b->queue = (WgItem *)(b->ws + align_up(need) + kAlign);
+  b->queue_cap = nitems;
   b->mixed = handles[0]->st.mixed;
   // stepped batches: the split form unless the members ask for the fused one
   // (one launch per pass, every workgroup folding its own QP's slots: cheaper
   // for few small QPs, dearer for many large ones; the autotuner decides)
   b->cfg = LaunchCfg{handles[0]->opt.form == GPCG_FORM_FUSED ? 0 : 1, 1, 1,
-                     default_chunk(handles[0]->opt), 3};
+                     default_chunk(handles[0]->opt), 0};
   if (handles[0]->opt.tiles_per_wg > 0) b->cfg.tiles_per_wg = handles[0]->opt.tiles_per_wg;
   b->cfg.cgk = handles[0]->opt.cg_kernel == GPCG_CGK_ON ? 1 : 0;
   b->cfg.spec = handles[0]->opt.prefetch == GPCG_PREFETCH_OFF ? 0 : 1;
@@ -1156,12 +1190,14 @@ int gpcg_batch_create(int count, const gpcg_handle *handles, void *workspace, si
     delete b;
     return rc;
   }
-  void *st = nullptr;
-  if (hipHostMalloc(&st, b->tbytes, hipHostMallocDefault) != hipSuccess) {
+  void *st = nullptr, *st_dev = nullptr;
+  rc = alloc_pinned(&st, &st_dev, b->tbytes + kAlign);
+  if (rc) {
     gpcg_batch_destroy(b);
-    return fail(GPCG_ERR_HIP, "hipHostMalloc of batch tables failed");
+    return rc;
   }
   b->stage = (char *)st;
+  b->stage_dev = (char *)st_dev;
   if (hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) != hipSuccess) {
     gpcg_batch_destroy(b);
@@ -1215,7 +1251,7 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       pre[i + 1] = pre[i] + w[i];
     }
     const int grid = pre[cnt];
-    HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
+    COPY_OK(b->ws, b->stage_dev, b->tbytes, b->stream);
     int pre = 0;
     for (int i = 0; i < cnt; ++i) pre |= b->hs[i]->st.dinv ? 1 : 0;
     PersistLaunch P{b->qptrs, b->prefix, cnt, grid, (int64_t)1 << 22, pre, 0};
@@ -1235,6 +1271,46 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
     bool split = b->cfg.split != 0;
     for (int i = 0; i < cnt; ++i) split = split || b->hs[i]->st.ntiles > kFusedMaxTiles;
     const int T = split ? b->cfg.tiles_per_wg : 1;
+    if (split && b->cfg.shrink == 0) {
+      // queue form: one launch table for the whole solve; every transition
+      // queues the work items of the QPs that are not done, and the data
+      // kernel (a fixed grid) runs them, so finished QPs cost nothing and
+      // the launch is never re-formed on the host
+      bool pre = false, mat = false;
+      for (int i = 0; i < cnt; ++i) {
+        qp[i] = b->hs[i]->dqp;
+        pre = pre || b->hs[i]->st.dinv != nullptr;
+        mat = mat || b->hs[i]->st.mrow != nullptr;
+      }
+      COPY_OK(b->ws, b->stage_dev, b->tbytes, b->stream);
+      COPY_OK(b->qcount, b->stage_dev + b->tbytes, 2 * sizeof(int32_t), b->stream);
+      const int spec = kVarQueue | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0) |
+                       (mat ? kVarMat : 0);
+      StepLaunch SL{};
+      SL.qps = b->qptrs;
+      SL.nqp = cnt;
+      SL.tiles_per_wg = T;
+      SL.item_tiles = T;
+      SL.queue = b->queue;
+      SL.qcount = b->qcount;
+      SL.queue_cap = (int32_t)b->queue_cap;
+      // one workgroup per item of the largest possible queue
+      SL.data_grid = 0;
+      for (int i = 0; i < cnt; ++i) SL.data_grid += (b->hs[i]->st.ntiles + T - 1) / T;
+      hipGraphExec_t graph = nullptr;
+      int rc = build_chain_graph(SL, b->mixed, spec, 1, chunk, &graph);
+      if (rc) return rc;
+      auto all_done = [&]() {
+        for (int i = 0; i < cnt; ++i)
+          if (!b->flags.host[i]) return false;
+        return true;
+      };
+      rc = run_until(b->stream, SL, b->mixed, spec, 1, chunk, graph, b->ev, all_done,
+                     (int64_t)1 << 26, &launches, &checks);
+      (void)hipGraphExecDestroy(graph);
+      if (rc) return rc;
+      active.clear();
+    }
     while (!active.empty()) {
       HIP_OK(hipStreamSynchronize(b->stream));  // the staged tables may still be in flight
       pre[0] = 0;
@@ -1247,7 +1323,7 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       const int total = pre[active.size()];
       auto *items = (WgItem *)(b->stage + items_offset(cnt));
       const int nitems = fill_items(items, qp, nt.data(), (int)active.size(), T);
-      HIP_OK(hipMemcpyAsync(b->ws, b->stage, b->tbytes, hipMemcpyHostToDevice, b->stream));
+      COPY_OK(b->ws, b->stage_dev, b->tbytes, b->stream);
       StepLaunch SL{};
       SL.qps = b->qptrs;
       SL.items = b->items;
@@ -1267,11 +1343,13 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       int rc = build_chain_graph(SL, b->mixed, spec, split ? 1 : 0, chunk, &graph);
       if (rc) return rc;
       // run until 1/shrink of this launch's tiles belong to finished QPs
+      // (shrink 0, the queue form's setting, in the fused form: until all are)
       auto enough = [&]() {
         int done_tiles = 0;
         for (int i : active)
           if (b->flags.host[i]) done_tiles += b->hs[i]->st.ntiles;
-        return (int64_t)b->cfg.shrink * done_tiles >= total;
+        return b->cfg.shrink > 0 ? (int64_t)b->cfg.shrink * done_tiles >= total
+                                 : done_tiles >= total;
       };
       rc = run_until(b->stream, SL, b->mixed, spec, split ? 1 : 0, chunk, graph, b->ev, enough,
                      (int64_t)1 << 26, &launches, &checks);
@@ -1323,8 +1401,7 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     int rc = GPCG_OK;
     for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
       for (int i = 0; i < cnt; ++i)
-        HIP_OK(hipMemcpyAsync(probs[i].x, x0s[i], sizeof(double) * (size_t)b->hs[i]->st.n,
-                              hipMemcpyDeviceToDevice, b->stream));
+        COPY_OK(probs[i].x, x0s[i], sizeof(double) * (size_t)b->hs[i]->st.n, b->stream);
       HIP_OK(hipStreamSynchronize(b->stream));
       const double t0 = now_s();
       rc = gpcg_batch_solve(b, probs, GPCG_BATCH_STEPPED, nullptr);
@@ -1384,7 +1461,7 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     c.chunk = ch;
     if ((rc = consider(c)) < 0) return rc;
   }
-  for (int sh : {3, 6, 12}) {
+  for (int sh : {0, 3, 6, 12}) {
     LaunchCfg c = best;
     c.shrink = sh;
     if ((rc = consider(c)) < 0) return rc;
@@ -1396,7 +1473,7 @@ int gpcg_batch_autotune(gpcg_batch b, const gpcg_problem *probs, const double *c
     if ((rc = consider(c)) < 0) return rc;
   }
   if (best.split && best.cgk)
-    for (int sh : {3, 6, 12}) {
+    for (int sh : {0, 3, 6, 12}) {
       LaunchCfg c = best;
       c.shrink = sh;
       if ((rc = consider(c)) < 0) return rc;
@@ -1455,10 +1532,12 @@ ReqLayout req_layout(const gpcg_operator *op, int precision) {
 
 struct SrvSlot {
   bool used = false;
+  bool retiring = false;  // done on the device; its answer is being copied out
   size_t off = 0, bytes = 0;
   gpcg_request req{};
   double t_submit = 0, t_admit = 0;
   int ntiles = 0;
+  int final_parity = 0;
 };
 
 struct SrvPending {
@@ -1467,26 +1546,56 @@ struct SrvPending {
   size_t bytes;
 };
 
+// Copies of finished requests' answers and states in flight on the stream,
+// completed when `ev` has passed.
+struct SrvRetire {
+  hipEvent_t ev;
+  std::vector<int> slots;
+};
+
 }  // namespace
 
+// The server runs the queue form of the split launch over a fixed device
+// table of max_slots QP pointers (null: an empty slot): every pass, the
+// transition kernel queues the work items of the resident requests that are
+// not done and the data kernel runs them, so a request that finishes costs
+// nothing for the rest of the chunk.  Chunks of `quantum` passes are queued as plain
+// launches (the data grid covers the running requests' tiles), at most two
+// chunks in flight; between them the host admits requests
+// (uploads queued on the stream, table entry set), notices finished ones
+// from their mapped done words, queues the copies of their answers and
+// states, and completes them once those copies have passed: nothing waits
+// for the whole stream.
 struct gpcg_server_s {
   gpcg_server_options opt;
   hipStream_t stream;
   char *arena;
-  size_t header;        // launch tables at the start of the arena
-  QPDev **qptrs;
-  int32_t *prefix;
-  WgItem *items;
+  size_t header;        // device table and work queue at the start of the arena
+  QPDev **qptrs;        // device table, max_slots entries
+  int32_t *qcount;      // device: the queue's two counters
+  WgItem *queue;        // device: 2 x item_cap items
   size_t item_cap;
-  char *stage_tables;   // pinned
+  QPDev **tab_host;     // host copy of the table
+  QPDev **tab_stage[2]; // pinned staging of table uploads
+  QPDev **tab_stage_dev[2];
+  hipEvent_t tab_ev[2] = {nullptr, nullptr};
+  int tab_next = 0;
+  bool tab_dirty = false;
   QPDev *stage;         // pinned, one per slot
-  PinnedWords flags;    // one DONE word per slot
+  QPDev *stage_dev;     // its device address
+  char *zeros_dev;      // device address of a pinned zero block
+  PinnedWords flags;    // one done word per slot
   std::vector<SrvSlot> slots;
-  std::deque<SrvPending> queue;
+  std::deque<SrvPending> queue_in;
   std::deque<gpcg_completion> done;
+  std::deque<SrvRetire> retiring;
+  std::vector<hipEvent_t> ev_pool;
   std::map<size_t, size_t> free_list;  // offset -> bytes, coalesced
-  int resident = 0;
-  int64_t launches = 0;  // parity of the next launch: launches & 1
+  int resident = 0;     // admitted and not yet completed (retiring included)
+  int running = 0;      // admitted and not yet noticed done
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+  int64_t chunks = 0;   // chunks issued
+  int64_t chunks_seen = 0;  // chunks known complete
   double tick_hz;
   gpcg_options solve_opt;
 
@@ -1518,6 +1627,16 @@ struct gpcg_server_s {
       }
     }
   }
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
 };
 
 namespace {
@@ -1532,14 +1651,14 @@ int srv_admit(gpcg_server_s *s, int slot_id, const SrvPending &p, size_t off) {
   const int64_t n = op_n(&op);
   hipStream_t st = s->stream;
   const size_t vb = 8 * (size_t)n;
-  HIP_OK(hipMemcpyAsync(base + R.b, rq.b, vb, hipMemcpyDeviceToDevice, st));
-  HIP_OK(hipMemcpyAsync(base + R.l, rq.l, vb, hipMemcpyDeviceToDevice, st));
-  HIP_OK(hipMemcpyAsync(base + R.u, rq.u, vb, hipMemcpyDeviceToDevice, st));
-  HIP_OK(hipMemcpyAsync(base + R.x0, rq.x0, vb, hipMemcpyDeviceToDevice, st));
+  COPY_OK(base + R.b, rq.b, vb, st);
+  COPY_OK(base + R.l, rq.l, vb, st);
+  COPY_OK(base + R.u, rq.u, vb, st);
+  COPY_OK(base + R.x0, rq.x0, vb, st);
   const size_t ex = (size_t)op.ny * (op.nx + 1), ey = (size_t)(op.ny + 1) * op.nx;
   if (op.kind == GPCG_OP_STENCIL5_VAR) {
-    HIP_OK(hipMemcpyAsync(base + R.wx, op.wx, 8 * ex, hipMemcpyDeviceToDevice, st));
-    HIP_OK(hipMemcpyAsync(base + R.wy, op.wy, 8 * ey, hipMemcpyDeviceToDevice, st));
+    COPY_OK(base + R.wx, op.wx, 8 * ex, st);
+    COPY_OK(base + R.wy, op.wy, 8 * ey, st);
     if (L.wx32 &&
         (gpcg_launch_convert_f32((const double *)(base + R.wx), (float *)(base + L.wx32),
                                  (int64_t)ex, st) ||
@@ -1547,6 +1666,8 @@ int srv_admit(gpcg_server_s *s, int slot_id, const SrvPending &p, size_t off) {
                                  (int64_t)ey, st)))
       return fail(GPCG_ERR_HIP, "FP32 weight conversion failed");
   }
+  // the slot's staging copy is free: its last use (the retirement of the
+  // request before) completed before the slot was released
   QPDev &q = s->stage[slot_id];
   std::memset(&q, 0, sizeof(q));
   QPStatic &S = q.st;
@@ -1585,62 +1706,100 @@ int srv_admit(gpcg_server_s *s, int slot_id, const SrvPending &p, size_t off) {
   initial_dyn(q.dyn[0]);
   initial_dyn(q.dyn[1]);
   s->flags.host[slot_id] = 0;
-  HIP_OK(hipMemcpyAsync(base + L.qp, &q, sizeof(QPDev), hipMemcpyHostToDevice, st));
+  COPY_OK(base + L.qp, &s->stage_dev[slot_id], sizeof(QPDev), st);
   sl.used = true;
+  sl.retiring = false;
   sl.off = off;
   sl.bytes = p.bytes;
   sl.req = rq;
   sl.t_submit = p.t_submit;
   sl.t_admit = now_s();
   sl.ntiles = L.ntiles;
+  s->tab_host[slot_id] = (QPDev *)(base + L.qp);
+  s->tab_dirty = true;
   s->resident += 1;
+  s->running += 1;
   return GPCG_OK;
 }
 
-// Moves finished requests to the completion list (after the stream is idle;
-// the last launch wrote the state of parity launches & 1).
-int srv_retire(gpcg_server_s *s) {
-  std::vector<int> fin;
-  for (int i = 0; i < (int)s->slots.size(); ++i)
-    if (s->slots[i].used && s->flags.host[i]) fin.push_back(i);
-  if (fin.empty()) return GPCG_OK;
-  const int par = (int)(s->launches & 1);
-  for (int i : fin) {
+// Requests whose done word is set: their answers and final states are copied
+// out behind the chunks already queued (the device never writes a finished
+// request's x again), and they leave the device table.
+int srv_notice_done(gpcg_server_s *s) {
+  SrvRetire r{};
+  for (int i = 0; i < (int)s->slots.size(); ++i) {
     SrvSlot &sl = s->slots[i];
+    if (!sl.used || sl.retiring) continue;
+    const int32_t w = s->flags.host[i];
+    if (!w) continue;
+    const int cur = (w >> 1) & 1;
+    sl.final_parity = (w >> 2) & 1;
     const ReqLayout R = req_layout(&sl.req.op, s->opt.precision);
     char *base = s->arena + sl.off;
+    if (sl.req.x_out)
+      COPY_OK(sl.req.x_out, base + (cur ? R.L.x1 : R.x0), 8 * (size_t)op_n(&sl.req.op),
+              s->stream);
     HIP_OK(hipMemcpyAsync(&s->stage[i], base + R.L.qp, sizeof(QPDev), hipMemcpyDeviceToHost,
                           s->stream));
+    sl.retiring = true;
+    s->tab_host[i] = nullptr;
+    s->tab_dirty = true;
+    s->running -= 1;
+    r.slots.push_back(i);
   }
-  HIP_OK(hipStreamSynchronize(s->stream));
-  for (int i : fin) {
-    SrvSlot &sl = s->slots[i];
-    const ReqLayout R = req_layout(&sl.req.op, s->opt.precision);
-    char *base = s->arena + sl.off;
-    const QPCore &d = s->stage[i].dyn[par].c;
-    if (sl.req.x_out)
-      HIP_OK(hipMemcpyAsync(sl.req.x_out, base + (d.cur ? R.L.x1 : R.x0),
-                            8 * (size_t)op_n(&sl.req.op), hipMemcpyDeviceToDevice, s->stream));
+  if (r.slots.empty()) return GPCG_OK;
+  r.ev = s->take_event();
+  if (!r.ev) return fail(GPCG_ERR_HIP, "hipEventCreate failed");
+  HIP_OK(hipEventRecord(r.ev, s->stream));
+  s->retiring.push_back(std::move(r));
+  return GPCG_OK;
+}
+
+// Completes the requests whose copies have passed; their slots and arena
+// space are free again.
+int srv_complete(gpcg_server_s *s) {
+  while (!s->retiring.empty()) {
+    SrvRetire &r = s->retiring.front();
+    const hipError_t e = hipEventQuery(r.ev);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return fail(GPCG_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+    const double t = now_s();
+    for (int i : r.slots) {
+      SrvSlot &sl = s->slots[i];
+      const QPDyn &dy = s->stage[i].dyn[sl.final_parity];
+      gpcg_completion c{};
+      c.tag = sl.req.tag;
+      fill_stats(s->stage[i].st, dy, s->tick_hz, &c.stats);
+      c.status = dy.c.status;
+      c.t_submit = sl.t_submit;
+      c.t_admit = sl.t_admit;
+      c.t_done = t;
+      c.stats.ms_total = (t - sl.t_admit) * 1e3;
+      s->done.push_back(c);
+      s->release(sl.off, sl.bytes);
+      sl.used = false;
+      sl.retiring = false;
+      s->flags.host[i] = 0;
+      s->resident -= 1;
+    }
+    s->ev_pool.push_back(r.ev);
+    s->retiring.pop_front();
   }
-  HIP_OK(hipStreamSynchronize(s->stream));
-  const double t = now_s();
-  for (int i : fin) {
-    SrvSlot &sl = s->slots[i];
-    const QPDyn &dy = s->stage[i].dyn[par];
-    gpcg_completion c{};
-    c.tag = sl.req.tag;
-    fill_stats(s->stage[i].st, dy, s->tick_hz, &c.stats);
-    c.status = dy.c.status;
-    c.t_submit = sl.t_submit;
-    c.t_admit = sl.t_admit;
-    c.t_done = t;
-    c.stats.ms_total = (t - sl.t_admit) * 1e3;
-    s->done.push_back(c);
-    s->release(sl.off, sl.bytes);
-    sl.used = false;
-    s->flags.host[i] = 0;
-    s->resident -= 1;
-  }
+  return GPCG_OK;
+}
+
+// Queues the upload of the device table when it changed (double-buffered
+// pinned staging: a staging copy is rewritten only after its last upload).
+int srv_upload_table(gpcg_server_s *s) {
+  if (!s->tab_dirty) return GPCG_OK;
+  const int k = s->tab_next;
+  HIP_OK(hipEventSynchronize(s->tab_ev[k]));
+  const size_t bytes = sizeof(QPDev *) * s->slots.size();
+  std::memcpy(s->tab_stage[k], s->tab_host, bytes);
+  COPY_OK(s->qptrs, s->tab_stage_dev[k], bytes, s->stream);
+  HIP_OK(hipEventRecord(s->tab_ev[k], s->stream));
+  s->tab_next ^= 1;
+  s->tab_dirty = false;
   return GPCG_OK;
 }
 
@@ -1672,8 +1831,10 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   // a resident request holds at least 24 bytes per unknown (x1, g0, g1), so
   // the arena holds at most arena / (24 * 256) tiles plus one partial tile per slot
   const size_t item_cap = (size_t)opt->max_slots + opt->arena_bytes / (24 * (size_t)kBlock);
-  const size_t header = tables_bytes(opt->max_slots, item_cap);
+  const size_t tab = align_up(sizeof(void *) * (size_t)opt->max_slots);
+  const size_t header = tab + queue_bytes(item_cap);
   if (opt->arena_bytes <= header) return fail(GPCG_ERR_WORKSPACE, "arena too small");
+  if (item_cap > (size_t)INT32_MAX) return fail(GPCG_ERR_ARG, "arena too large for the work queue");
   auto *s = new gpcg_server_s();
   s->opt = *opt;
   if (s->opt.quantum <= 0) s->opt.quantum = 64;
@@ -1681,8 +1842,8 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   s->arena = (char *)opt->arena;
   s->header = header;
   s->qptrs = (QPDev **)s->arena;
-  s->prefix = (int32_t *)(s->arena + align_up(sizeof(void *) * (size_t)opt->max_slots));
-  s->items = (WgItem *)(s->arena + items_offset(opt->max_slots));
+  s->qcount = (int32_t *)(s->arena + tab);
+  s->queue = (WgItem *)(s->arena + tab + kAlign);
   s->item_cap = item_cap;
   s->slots.resize(opt->max_slots);
   s->free_list[header] = opt->arena_bytes - header;
@@ -1690,14 +1851,32 @@ int gpcg_server_create(const gpcg_server_options *opt, void *stream, gpcg_server
   gpcg_options_default(&s->solve_opt);
   s->solve_opt.tol_rel = opt->tol_rel;
   s->solve_opt.precision = opt->precision;
+  s->tab_host = new QPDev *[opt->max_slots]();
   int rc = alloc_flag(&s->flags, (size_t)opt->max_slots);
-  void *st = nullptr, *tb = nullptr;
-  if (!rc && (hipHostMalloc(&st, sizeof(QPDev) * opt->max_slots, hipHostMallocDefault) !=
-                  hipSuccess ||
-              hipHostMalloc(&tb, header, hipHostMallocDefault) != hipSuccess))
-    rc = fail(GPCG_ERR_HIP, "hipHostMalloc for the server failed");
+  void *st = nullptr, *st_dev = nullptr;
+  const size_t tbytes = sizeof(QPDev *) * (size_t)opt->max_slots;
+  if (!rc) rc = alloc_pinned(&st, &st_dev, sizeof(QPDev) * opt->max_slots);
   s->stage = (QPDev *)st;
-  s->stage_tables = (char *)tb;
+  s->stage_dev = (QPDev *)st_dev;
+  for (int k = 0; !rc && k < 2; ++k) {
+    void *t = nullptr, *td = nullptr;
+    rc = alloc_pinned(&t, &td, tbytes + kAlign);  // the extra block stays zero
+    s->tab_stage[k] = (QPDev **)t;
+    s->tab_stage_dev[k] = (QPDev **)td;
+  }
+  if (!rc) s->zeros_dev = (char *)s->tab_stage_dev[1] + tbytes;
+  for (int k = 0; !rc && k < 2; ++k)
+    if (hipEventCreateWithFlags(&s->tab_ev[k], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->chunk_ev[k], hipEventDisableTiming) != hipSuccess)
+      rc = fail(GPCG_ERR_HIP, "hipEventCreate failed");
+  if (!rc) {
+    // an empty table and a zero queue count, then the chunk graph over them
+    std::memset(s->tab_stage[0], 0, tbytes);
+    if (gpcg_launch_copy(s->qptrs, s->tab_stage_dev[0], tbytes, s->stream) != 0 ||
+        gpcg_launch_copy(s->qcount, s->zeros_dev, 2 * sizeof(int32_t), s->stream) != 0 ||
+        hipEventRecord(s->tab_ev[0], s->stream) != hipSuccess)
+      rc = fail(GPCG_ERR_HIP, "server table initialisation failed");
+  }
   if (rc) {
     gpcg_server_destroy(s);
     return rc;
@@ -1714,75 +1893,68 @@ int gpcg_server_submit(gpcg_server s, const gpcg_request *req) {
   if (!req->b || !req->l || !req->u || !req->x0) return fail(GPCG_ERR_ARG, "request arrays");
   if (bytes > s->opt.arena_bytes - s->header)
     return fail(GPCG_ERR_NOSPACE, "request footprint exceeds the arena");
-  s->queue.push_back(SrvPending{*req, now_s(), bytes});
+  s->queue_in.push_back(SrvPending{*req, now_s(), bytes});
   return GPCG_OK;
 }
 
 int gpcg_server_step(gpcg_server s, int *active) {
   if (!s) return fail(GPCG_ERR_ARG, "server is NULL");
-  int rc = GPCG_OK;
-  // admission: FIFO, by free slot and arena space
-  while (!s->queue.empty() && s->resident < s->opt.max_slots) {
-    size_t off = 0;
-    if (!s->alloc(s->queue.front().bytes, &off)) break;
+  int rc = srv_notice_done(s);
+  if (!rc) rc = srv_complete(s);
+  if (rc) return rc;
+  // admission: FIFO, by free slot and arena space; a new request starts at
+  // the next chunk, whose first launch has parity 0 (chunks are even)
+  while (!s->queue_in.empty()) {
     int slot = -1;
     for (int i = 0; i < (int)s->slots.size(); ++i)
       if (!s->slots[i].used) {
         slot = i;
         break;
       }
-    // a new request starts at the parity of the next launch
-    if (s->launches & 1) {
-      // keep the launch count even at admission: one empty launch is never
-      // needed because quanta are even; this branch documents the invariant
-      return fail(GPCG_ERR_ARG, "internal: odd launch count at admission");
-    }
-    rc = srv_admit(s, slot, s->queue.front(), off);
+    if (slot < 0) break;
+    size_t off = 0;
+    if (!s->alloc(s->queue_in.front().bytes, &off)) break;
+    rc = srv_admit(s, slot, s->queue_in.front(), off);
     if (rc) return rc;
-    s->queue.pop_front();
+    s->queue_in.pop_front();
   }
-  if (s->resident > 0) {
-    auto **qp = (QPDev **)s->stage_tables;
-    auto *pre = (int32_t *)(s->stage_tables + align_up(sizeof(void *) * s->slots.size()));
-    int cnt = 0;
-    bool spec = true;
-    pre[0] = 0;
-    std::vector<int32_t> nt;
-    for (int i = 0; i < (int)s->slots.size(); ++i) {
-      if (!s->slots[i].used) continue;
-      spec = spec && req_layout(&s->slots[i].req.op, s->opt.precision).L.tile == kBlock;
-      const ReqLayout R = req_layout(&s->slots[i].req.op, s->opt.precision);
-      qp[cnt] = (QPDev *)(s->arena + s->slots[i].off + R.L.qp);
-      pre[cnt + 1] = pre[cnt] + s->slots[i].ntiles;
-      nt.push_back(s->slots[i].ntiles);
-      ++cnt;
+  rc = srv_upload_table(s);
+  if (rc) return rc;
+  if (s->running > 0) {
+    // at most two chunks in flight: wait for the older one before queuing
+    if (s->chunks - s->chunks_seen >= 2) {
+      HIP_OK(hipEventSynchronize(s->chunk_ev[s->chunks_seen & 1]));
+      s->chunks_seen += 1;
     }
-    if ((size_t)pre[cnt] > s->item_cap)
-      return fail(GPCG_ERR_ARG, "internal: more tiles resident than the item table holds");
-    auto *items = (WgItem *)(s->stage_tables + items_offset((int)s->slots.size()));
-    const int nitems = fill_items(items, qp, nt.data(), cnt, 1);
-    HIP_OK(hipMemcpyAsync(s->arena, s->stage_tables, s->header, hipMemcpyHostToDevice,
-                          s->stream));
+    // the data kernel's grid covers the work items of every request still
+    // running (one workgroup each); the queue can only shrink within a chunk
+    int64_t tiles = 0;
+    for (int i = 0; i < (int)s->slots.size(); ++i)
+      if (s->tab_host[i]) tiles += s->slots[i].ntiles;
     StepLaunch SL{};
     SL.qps = s->qptrs;
-    SL.items = s->items;
-    SL.nqp = cnt;
-    SL.total_tiles = pre[cnt];
+    SL.nqp = (int32_t)s->slots.size();
     SL.tiles_per_wg = 1;
-    SL.data_grid = nitems;
-    // the split form: with requests of up to 1024 tiles resident, the fused
-    // form would have every workgroup of a large request sum all its slots
+    SL.item_tiles = 1;
+    SL.queue = s->queue;
+    SL.qcount = s->qcount;
+    SL.queue_cap = (int32_t)s->item_cap;
+    SL.data_grid = (int32_t)std::max<int64_t>(1, tiles);
+    const int mixed = s->opt.precision == GPCG_PREC_MIXED ? 1 : 0;
     for (int k = 0; k < s->opt.quantum; ++k) {
-      SL.parity = (int)(s->launches & 1);
-      if (gpcg_launch_split(SL, s->opt.precision == GPCG_PREC_MIXED, spec, s->stream) != 0)
+      SL.parity = k & 1;
+      if (gpcg_launch_split(SL, mixed, kVarQueue, s->stream) != 0)
         return fail(GPCG_ERR_HIP, "pass kernel launch failed");
-      s->launches += 1;
     }
-    HIP_OK(hipStreamSynchronize(s->stream));
-    rc = srv_retire(s);
+    HIP_OK(hipEventRecord(s->chunk_ev[s->chunks & 1], s->stream));
+    s->chunks += 1;
+  } else if (!s->retiring.empty() && s->queue_in.empty()) {
+    // nothing left to run: wait for the copies of the last answers
+    HIP_OK(hipEventSynchronize(s->retiring.back().ev));
+    rc = srv_complete(s);
     if (rc) return rc;
   }
-  if (active) *active = (int)s->queue.size() + s->resident;
+  if (active) *active = (int)s->queue_in.size() + s->resident;
   return GPCG_OK;
 }
 
@@ -1800,8 +1972,15 @@ int gpcg_server_poll(gpcg_server s, gpcg_completion *out, int max, int *got) {
 int gpcg_server_destroy(gpcg_server s) {
   if (!s) return GPCG_OK;
   (void)hipStreamSynchronize(s->stream);
+  for (auto &r : s->retiring) (void)hipEventDestroy(r.ev);
+  for (auto e : s->ev_pool) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k) {
+    if (s->tab_ev[k]) (void)hipEventDestroy(s->tab_ev[k]);
+    if (s->chunk_ev[k]) (void)hipEventDestroy(s->chunk_ev[k]);
+    if (s->tab_stage[k]) (void)hipHostFree(s->tab_stage[k]);
+  }
+  delete[] s->tab_host;
   if (s->stage) (void)hipHostFree(s->stage);
-  if (s->stage_tables) (void)hipHostFree(s->stage_tables);
   if (s->flags.host) (void)hipHostFree(s->flags.host);
   delete s;
   return GPCG_OK;
