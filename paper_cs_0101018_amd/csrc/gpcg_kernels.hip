@@ -1422,16 +1422,13 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   }
   const int par = L.parity;
   double *slots = tile_slots(q);
-  // Every load that does not depend on the state is issued first, together:
-  // this thread's word of the state and of the static part (clamped to a
-  // word inside the struct; only the threads that own a word store it), the
-  // slots of tile tid, and the early CG operands; the LDS copies are written
-  // once they arrive.
-  const int tid = (int)threadIdx.x;
-  const int sw = tid - (kBlock - kStaticWords);
-  const uint32_t dyn_w = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par]))
-      [tid < kDynWords ? tid : kDynWords - 1];
-  const uint32_t st_w = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw >= 0 ? sw : 0];
+  // The state is copied first and the slot loads are issued after it has
+  // arrived.  Issuing them all together (the order of the transition kernel)
+  // gave, now and then, wrong sums in the second pass of a solve that
+  // followed another solve on the same workspace (2048 tiles, several XCDs
+  // reading slots the first pass had just written); the order below has not.
+  copy_dyn(&q->dyn[par], &sd);
+  copy_static(&q->st, &ss);
   double pf[kNP];
   prefetch_slot(slots, par, pf);
   const uint64_t clk = wall_clock64();
@@ -1442,8 +1439,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   const bool own = SPEC && kk < V.n;
   CGOperands<CT> P{};
   if (own) cg_prefetch<CT, PRE>(V, par, kk, P);
-  if (tid < kDynWords) reinterpret_cast<uint32_t *>(&sd)[tid] = dyn_w;
-  if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
   __syncthreads();
   const QPStatic *S = &ss;
   const int ntiles = S->ntiles, mixed = S->mixed;

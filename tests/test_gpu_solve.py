@@ -235,11 +235,7 @@ def test_errors():
     assert st["status"] == gpcg.GPCG_MAXIT and st["outer_iters"] == 1
 
 
-@pytest.mark.parametrize("form", [
-    pytest.param(1, marks=pytest.mark.xfail(
-        reason="fused form: a repeated solve of a 2048-tile grid on one handle "
-               "can start from a wrong tile partial (open defect)", strict=False)),
-    2], ids=["fused", "split"])
+@pytest.mark.parametrize("form", [1, 2], ids=["fused", "split"])
 def test_repeated_solves_on_one_handle(form):
     """Several solves on one handle and workspace (the state of the last one
     still in the caches) give the same answer every time.  A 1024^2 grid in
@@ -251,7 +247,7 @@ def test_repeated_solves_on_one_handle(form):
     b, l, u, x0 = (G.to_dev(a) for a in (inst.b, inst.l, inst.u, inst.x0))
     s = gpcg.Solver(gpcg.Operator.stencil_const(1024, 1024, inst.w), device=dev, form=form)
     first = None
-    for rep in range(3):
+    for rep in range(6):
         print(f"repeated solve form={form} rep={rep}", flush=True)
         x = x0.clone()
         st = s.solve(b, l, u, x)
