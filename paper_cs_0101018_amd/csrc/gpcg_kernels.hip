@@ -332,6 +332,15 @@ __device__ __forceinline__ void prefetch_slot(const double *slots, int par, doub
   for (int k = 0; k < kNP; ++k) pf[k] = sl[slot_index((int)threadIdx.x, par, k)];
 }
 
+// Loads the first ns slots of tile `tid` of parity par (always present); the
+// others are zero.
+__device__ __forceinline__ void prefetch_slots(const double *slots, int par, int ns,
+                                               double (&pf)[kNP]) {
+  const gptr<const double> sl = gbl(slots);
+#pragma unroll
+  for (int k = 0; k < kNP; ++k) pf[k] = k < ns ? sl[slot_index((int)threadIdx.x, par, k)] : 0.0;
+}
+
 // Adds slots t = tid + 256, tid + 512, ... (in that order) of parity par to
 // res / vf, issuing the loads of D slots at a time before adding them.
 template <int NS, int D = (NS <= 3 ? 8 : 2)>
@@ -1422,15 +1431,23 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
   }
   const int par = L.parity;
   double *slots = tile_slots(q);
-  // The state is copied first and the slot loads are issued after it has
-  // arrived.  Issuing them all together (the order of the transition kernel)
-  // gave, now and then, wrong sums in the second pass of a solve that
-  // followed another solve on the same workspace (2048 tiles, several XCDs
-  // reading slots the first pass had just written); the order below has not.
-  copy_dyn(&q->dyn[par], &sd);
-  copy_static(&q->st, &ss);
-  double pf[kNP];
-  prefetch_slot(slots, par, pf);
+  // The state and the static part are copied first; the slots are loaded
+  // once the state is in LDS, and only those the pending pass filled.
+  // Issuing the slot loads together with the state loads (the order of the
+  // transition kernel) gave, now and then, wrong sums in the second pass of a
+  // solve that followed another solve on the same workspace (2048 tiles,
+  // several XCDs reading slots the first pass had just written); this order
+  // has not.
+  {
+    const int tid = (int)threadIdx.x;
+    const int sw = tid - (kBlock - kStaticWords);
+    uint32_t dw = 0, stw = 0;
+    if (tid < kDynWords) dw = gbl(reinterpret_cast<const uint32_t *>(&q->dyn[par]))[tid];
+    if (sw >= 0) stw = gbl(reinterpret_cast<const uint32_t *>(&q->st))[sw];
+    if (tid < kDynWords) reinterpret_cast<uint32_t *>(&sd)[tid] = dw;
+    if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = stw;
+  }
+  __asm__ volatile("" ::: "memory");  // the slot loads stay behind the copies
   const uint64_t clk = wall_clock64();
   // SPEC launches hold only stencil QPs with one unknown per thread; the CG
   // view is read from the state with uniform (scalar) loads
@@ -1452,6 +1469,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch L) {
     else if (sd.c.phase == PH_GP_TRIAL) gcp = sd.c.cur ^ 1;
     if (gcp >= 0 && own) gp_prefetch(S, gcp, kk, G);
   }
+  double pf[kNP];
+  prefetch_slots(slots, par, sd.c.pending ? nslots(sd.c.phase) : 0, pf);
   if (sd.c.pending) {
     double R[kNP];
     sum_partials(slots, par, ntiles, sd.c.phase, f32_slots(mixed, sd.c.phase), pf, R);
