@@ -591,8 +591,12 @@ def bench_batch(args, gpcg, torch, dev, mixed, sample=()):
         sys.exit("the matrix free set needs CSR operators; the batch members are stencils")
     fs = gpcg.GPCG_FREESET_LIST if args.free_set == "list" else gpcg.GPCG_FREESET_MASK
     pc = gpcg.GPCG_PRECOND_JACOBI if args.precond == "jacobi" else gpcg.GPCG_PRECOND_NONE
-    solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed), free_set=fs, precond=pc)
-               for d in data]
+    # batch members use 512-unknown tiles (the split form's data kernel keeps
+    # two 256-unknown chunks of loads in flight per workgroup); the compacted
+    # list form keeps its 256-unknown tiles
+    tile = 512 if fs == gpcg.GPCG_FREESET_MASK else 0
+    solvers = [gpcg.Solver(d[0], device=dev, precision=int(mixed), free_set=fs, precond=pc,
+                           tile=tile) for d in data]
     batch = gpcg.Batch(solvers, device=dev)
     xs = [torch.empty_like(d[4]) for d in data]
     probs = [(d[1], d[2], d[3], x) for d, x in zip(data, xs)]
@@ -629,7 +633,7 @@ def bench_batch(args, gpcg, torch, dev, mixed, sample=()):
                 "in [32, 384], seed 0)",
         "config": {"workload": wl, "qps": len(insts), "unknowns": n_tot,
                    "batch_mode": args.batch_mode, "free_set": args.free_set,
-                   "precond": args.precond},
+                   "precond": args.precond, "tile": tile or "auto"},
         "roofline": {"bound": "hbm", "kernel": "whole batch (every pass of every QP)",
                      "achieved": round(alg_bytes / wall / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg_bytes / wall / 1e9 / HBM_PEAK_GBS, 4),

@@ -366,7 +366,11 @@ int gpcg_batch_destroy(gpcg_batch bt);
 /* ------------------------------------------------------------ serving */
 /* Continuous batching: requests are admitted while others run, as slots and
  * arena memory free up; every request's state stays resident in the arena
- * until it completes.  The caller drives the loop with gpcg_server_step. */
+ * until it completes.  The caller drives the loop with gpcg_server_step.
+ * Requests are laid out with 512-unknown tiles (GPCG_SERVER_TILE) whatever
+ * their size, so a served answer is bitwise that of a solo solve with
+ * options.tile = GPCG_SERVER_TILE. */
+#define GPCG_SERVER_TILE 512
 typedef struct gpcg_server_s *gpcg_server;
 
 typedef struct {

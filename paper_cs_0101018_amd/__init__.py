@@ -42,6 +42,7 @@ GPCG_PRECOND_NONE, GPCG_PRECOND_JACOBI = 0, 1
 GPCG_CGSTOP_DECREASE, GPCG_CGSTOP_RESIDUAL = 0, 1
 GPCG_LOOKAHEAD_AUTO, GPCG_LOOKAHEAD_ON, GPCG_LOOKAHEAD_OFF = 0, 1, 2
 GPCG_CGK_AUTO, GPCG_CGK_ON, GPCG_CGK_OFF = 0, 1, 2
+GPCG_SERVER_TILE = 512  # tile of every served request
 
 
 class gpcg_operator(C.Structure):

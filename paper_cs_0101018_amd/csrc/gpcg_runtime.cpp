@@ -1507,9 +1507,14 @@ struct ReqLayout {
   size_t b, l, u, x0, wx, wy, total;
 };
 
+// Served requests always run in the split form, whose data kernel keeps the
+// loads of two 256-unknown chunks in flight per workgroup with 512-unknown
+// tiles; the fused form's reasons for 256-unknown tiles on small QPs (early
+// operand loads, look-ahead) do not apply.
 ReqLayout req_layout(const gpcg_operator *op, int precision) {
+  static_assert(GPCG_SERVER_TILE % kBlock == 0, "server tile");
   ReqLayout R{};
-  R.L = layout_for(op, precision, 0, GPCG_FREESET_MASK, GPCG_PRECOND_NONE);
+  R.L = layout_for(op, precision, GPCG_SERVER_TILE, GPCG_FREESET_MASK, GPCG_PRECOND_NONE);
   const int64_t n = op_n(op);
   size_t off = R.L.total;
   auto take = [&](size_t bytes) {

@@ -134,7 +134,8 @@ def test_server_mix_equals_alone():
     for c in done:
         inst = insts[c["tag"]]
         assert c["status"] == 0
-        xa, ga, sa = solo(inst, precision=gpcg.GPCG_PREC_MIXED, tol_rel=1e-8)
+        xa, ga, sa = solo(inst, precision=gpcg.GPCG_PREC_MIXED, tol_rel=1e-8,
+                          tile=gpcg.GPCG_SERVER_TILE)
         assert np.array_equal(outs[c["tag"]].cpu().numpy(), xa), inst.name
         assert c["stats"]["cg_iters"] == sa["cg_iters"]
     # a request that can never fit is refused
