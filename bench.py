@@ -452,9 +452,10 @@ def kernel_names(gpcg, args, tuned, ntiles, mixed, csr, precond):
     # form never runs in the CG-only kernel
     part = 1 if cgk and mat == "false" else 0
     pmat = "false" if part == 1 else mat
-    return (f"gpcg::pass_kernel<{flags}, {part}, {pmat}> (data kernel of the split form; "
-            "the time per launch is that of one pass: transition and data kernels)",
-            f"pass_kernel<{flags}, {part}, {pmat}>")
+    # the last template argument: one QP, no work queue
+    return (f"gpcg::pass_kernel<{flags}, {part}, {pmat}, false> (data kernel of the split "
+            "form; the time per launch is that of one pass: transition and data kernels)",
+            f"pass_kernel<{flags}, {part}, {pmat}, false>")
 
 
 def run_single(gpcg, torch, dev, args, workload, steps, warmup, autotune=True):
