@@ -65,6 +65,10 @@ WORKLOADS = {
                           "u=0.25+0.05 U(0,1), x0=max(l,0), tol 1e-8 rel"),
     "obstacle1600_mixed": ("obstacle_ub_1600", dict(precision=1),
                            "GPCG mixed FP32-CG, obstacle 1600x1600, both bounds"),
+    # the same problem family past the 256 MB last-level cache (1.34 GB of
+    # vectors per pass): every pass streams from HBM
+    "obstacle4096_fp64": ("obstacle_ub_4096", dict(),
+                          "GPCG FP64, obstacle 4096x4096 (n=16,777,216), both bounds, tol 1e-8 rel"),
     "bearing256_fp64": ("bearing256", dict(), "GPCG FP64, -div(c grad u) 256x256, "
                         "c=(1+0.9 cos 2 pi s)^3 (eccentricity 0.9), l=0, u=inf, tol 1e-8 rel"),
     # small free set, CSR operator (the matrix free set's case)
