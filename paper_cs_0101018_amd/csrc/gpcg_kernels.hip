@@ -2066,6 +2066,23 @@ __global__ __launch_bounds__(kBlock) void spmv_march_kernel(const OpView<T> A,
 // so each thread keeps 4 * kPgradUnroll loads in flight.
 constexpr int kPgradUnroll = 4;
 
+// The face sums of unknown k in one thread's accumulators (in the order the
+// thread meets its unknowns).
+__device__ __forceinline__ void pgrad_add(double xk, double lk, double uk, double gk, double *pg,
+                                          int64_t k, double (&acc)[4]) {
+  const double p = proj_grad(xk, lk, uk, gk);
+  if (pg) pg[k] = p;
+  acc[0] = __fma_rn(p, p, acc[0]);
+  acc[1] += (xk == lk) ? 1.0 : 0.0;
+  acc[2] += (xk != lk && xk == uk) ? 1.0 : 0.0;
+  acc[3] += (is_active(xk, lk, uk) && !is_binding(xk, lk, uk, gk)) ? 1.0 : 0.0;
+}
+
+// PAIR: x, l, u, g (and pg) are 16-byte aligned; each load brings two
+// consecutive unknowns (2j, 2j + 1), kPgradUnroll pairs per thread and loop
+// trip, so every thread keeps 4 * kPgradUnroll 16-byte loads in flight; an odd
+// last unknown is added by thread 0 of workgroup 0 after its loop.
+template <bool PAIR>
 __global__ __launch_bounds__(kBlock) void pgrad_kernel(int64_t n, const double *__restrict__ x,
                                                        const double *__restrict__ l,
                                                        const double *__restrict__ u,
@@ -2074,29 +2091,53 @@ __global__ __launch_bounds__(kBlock) void pgrad_kernel(int64_t n, const double *
                                                        double *__restrict__ part) {
   constexpr int U = kPgradUnroll;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t step = (int64_t)gridDim.x * kBlock * U;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock * U + threadIdx.x; base < n; base += step) {
-    double xv[U], lv[U], uv[U], gv[U];
+  if constexpr (PAIR) {
+    const int64_t np = n / 2;
+    const double2 *x2 = reinterpret_cast<const double2 *>(x);
+    const double2 *l2 = reinterpret_cast<const double2 *>(l);
+    const double2 *u2 = reinterpret_cast<const double2 *>(u);
+    const double2 *g2 = reinterpret_cast<const double2 *>(g);
+    const int64_t step = (int64_t)gridDim.x * kBlock * U;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock * U + threadIdx.x; base < np; base += step) {
+      double2 xv[U], lv[U], uv[U], gv[U];
 #pragma unroll
-    for (int e = 0; e < U; ++e) {
-      const int64_t k = base + (int64_t)e * kBlock;
-      const int64_t kc = k < n ? k : n - 1;
-      xv[e] = x[kc];
-      lv[e] = l[kc];
-      uv[e] = u[kc];
-      gv[e] = g[kc];
+      for (int e = 0; e < U; ++e) {
+        const int64_t j = base + (int64_t)e * kBlock;
+        const int64_t jc = j < np ? j : np - 1;
+        xv[e] = x2[jc];
+        lv[e] = l2[jc];
+        uv[e] = u2[jc];
+        gv[e] = g2[jc];
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int64_t j = base + (int64_t)e * kBlock;
+        if (j >= np) break;
+        pgrad_add(xv[e].x, lv[e].x, uv[e].x, gv[e].x, pg, 2 * j, acc);
+        pgrad_add(xv[e].y, lv[e].y, uv[e].y, gv[e].y, pg, 2 * j + 1, acc);
+      }
     }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+      pgrad_add(x[n - 1], l[n - 1], u[n - 1], g[n - 1], pg, n - 1, acc);
+  } else {
+    const int64_t step = (int64_t)gridDim.x * kBlock * U;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock * U + threadIdx.x; base < n; base += step) {
+      double xv[U], lv[U], uv[U], gv[U];
 #pragma unroll
-    for (int e = 0; e < U; ++e) {
-      const int64_t k = base + (int64_t)e * kBlock;
-      if (k >= n) break;
-      const double xk = xv[e], lk = lv[e], uk = uv[e], gk = gv[e];
-      const double p = proj_grad(xk, lk, uk, gk);
-      if (pg) pg[k] = p;
-      acc[0] = __fma_rn(p, p, acc[0]);
-      acc[1] += (xk == lk) ? 1.0 : 0.0;
-      acc[2] += (xk != lk && xk == uk) ? 1.0 : 0.0;
-      acc[3] += (is_active(xk, lk, uk) && !is_binding(xk, lk, uk, gk)) ? 1.0 : 0.0;
+      for (int e = 0; e < U; ++e) {
+        const int64_t k = base + (int64_t)e * kBlock;
+        const int64_t kc = k < n ? k : n - 1;
+        xv[e] = x[kc];
+        lv[e] = l[kc];
+        uv[e] = u[kc];
+        gv[e] = g[kc];
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int64_t k = base + (int64_t)e * kBlock;
+        if (k >= n) break;
+        pgrad_add(xv[e], lv[e], uv[e], gv[e], pg, k, acc);
+      }
     }
   }
   block_sum<double, 4>(acc);
@@ -2308,13 +2349,36 @@ int gpcg_launch_spmv(const QPDev *dqp, const QPStatic *S, int64_t n, const void 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+namespace {
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// The partial-sum kernel of the projected-gradient reduction: 16-byte loads
+// of unknown pairs when every array is 16-byte aligned, else 8-byte loads.
+// Returns the number of workgroups (at most kPgradMaxBlocks), whose partials
+// land in part.
+int launch_pgrad_partials(int64_t n, const double *x, const double *l, const double *u,
+                          const double *g, double *pg, double *part, void *stream) {
+  const bool pair = aligned16(x) && aligned16(l) && aligned16(u) && aligned16(g) &&
+                    (!pg || aligned16(pg));
+  const int64_t per_wg_trip = (int64_t)kPgradUnroll * (pair ? 2 : 1);
+  int grid = grid_for((n + per_wg_trip - 1) / per_wg_trip);
+  if (grid > kPgradMaxBlocks) grid = kPgradMaxBlocks;
+  if (pair)
+    hipLaunchKernelGGL(pgrad_kernel<true>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x,
+                       l, u, g, pg, part);
+  else
+    hipLaunchKernelGGL(pgrad_kernel<false>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n,
+                       x, l, u, g, pg, part);
+  return grid;
+}
+
+}  // namespace
+
 int gpcg_launch_pgrad(int64_t n, const double *x, const double *l, const double *u,
                       const double *g, double *pg, double *part, double *out4, void *stream) {
   if (n <= 0) return -1;
-  int grid = grid_for((n + kPgradUnroll - 1) / kPgradUnroll);
-  if (grid > kPgradMaxBlocks) grid = kPgradMaxBlocks;
-  hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x, l, u,
-                     g, pg, part);
+  const int grid = launch_pgrad_partials(n, x, l, u, g, pg, part, stream);
   hipLaunchKernelGGL(pgrad_final_kernel, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
                      part, out4);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -2363,14 +2427,11 @@ int gpcg_launch_pgrad_scratch(int64_t n, const double *x, const double *l, const
   double *base = scratch_on_current_device(&err);
   if (!base) return err;
   if (n <= 0) return -3;
-  int grid = grid_for((n + kPgradUnroll - 1) / kPgradUnroll);
-  if (grid > kPgradMaxBlocks) grid = kPgradMaxBlocks;
   double *part = base;
   double *tot = base + 4 * kPgradMaxBlocks;
   // every slot the final kernel reads (4 per launched workgroup) is written by
   // the first kernel: nothing needs clearing between calls
-  hipLaunchKernelGGL(pgrad_kernel, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x, l, u,
-                     g, pg, part);
+  const int grid = launch_pgrad_partials(n, x, l, u, g, pg, part, stream);
   hipLaunchKernelGGL(pgrad_final_kernel, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
                      (const double *)part, tot);
   *out4 = tot;

@@ -189,9 +189,12 @@ def test_spmv_bench_size_8192():
     s.close()
 
 
+@pytest.mark.parametrize("offset", [0, 1], ids=["aligned16", "aligned8"])
 @pytest.mark.parametrize("n", [1, 255, 256, 257, 5000, 70001, 5_000_001])
-def test_projected_gradient_exact(n):
-    """Projected gradient and face counts are compare/select work: bit-exact."""
+def test_projected_gradient_exact(n, offset):
+    """Projected gradient and face counts are compare/select work: bit-exact.
+    offset 1 passes arrays one element into their buffers (8-byte aligned
+    only): the kernel's 8-byte-load path instead of its unknown-pair path."""
     import paper_cs_0101018_amd as gpcg
     torch, dev = G.torch_dev()
     rng = np.random.default_rng(n)
@@ -212,8 +215,12 @@ def test_projected_gradient_exact(n):
     s = gpcg.Solver(gpcg.Operator.csr(G.to_dev(np.arange(n + 1, dtype=np.int32)),
                                       G.to_dev(np.arange(n, dtype=np.int32)),
                                       G.to_dev(np.ones(n))), device=dev)
-    pg = torch.empty(n, dtype=torch.float64, device=dev)
-    n2, lo, up, nb = s.projected_gradient(G.to_dev(x), G.to_dev(l), G.to_dev(u), G.to_dev(g), pg)
+    def dev_vec(a):
+        t = torch.zeros(n + offset, dtype=torch.float64, device=dev)
+        t[offset:] = G.to_dev(a)
+        return t[offset:]
+    pg = dev_vec(np.zeros(n))
+    n2, lo, up, nb = s.projected_gradient(dev_vec(x), dev_vec(l), dev_vec(u), dev_vec(g), pg)
     want = ora.proj_gradient(x, l, u, g)
     assert np.array_equal(pg.cpu().numpy(), want)
     assert (lo, up, nb) == ora.classify(x, l, u, g)
