@@ -71,6 +71,12 @@ WORKLOADS = {
                           "GPCG FP64, obstacle 4096x4096 (n=16,777,216), both bounds, tol 1e-8 rel"),
     "bearing256_fp64": ("bearing256", dict(), "GPCG FP64, -div(c grad u) 256x256, "
                         "c=(1+0.9 cos 2 pi s)^3 (eccentricity 0.9), l=0, u=inf, tol 1e-8 rel"),
+    # the coefficient family of the paper's journal-bearing runs at their size
+    # (1600^2); finite differences, not the paper's finite elements: context
+    "varcoef1600_fp64": ("varcoef1600", dict(), "GPCG FP64, -div(c grad u) 1600x1600, "
+                         "c=(1+0.1 cos 2 pi s)^3 (eccentricity 0.1), l=0, u=inf, tol 1e-8 rel"),
+    "bearing1600_fp64": ("bearing1600", dict(), "GPCG FP64, -div(c grad u) 1600x1600, "
+                         "c=(1+0.9 cos 2 pi s)^3 (eccentricity 0.9), l=0, u=inf, tol 1e-8 rel"),
     # small free set, CSR operator (the matrix free set's case)
     "pressed512_csr_fp64": ("pressed512", dict(operator="csr"),
                             "GPCG FP64, obstacle 512x512 pressed onto its obstacle (b=-1e4), "
@@ -183,6 +189,10 @@ def make_instance(key):
         return instances.varcoef256(0)
     if key == "bearing256":
         return instances.varcoef(256, 0, eps=0.9, name="bearing256")
+    if key == "varcoef1600":
+        return instances.varcoef(1600, 0, eps=0.1, name="varcoef1600")
+    if key == "bearing1600":
+        return instances.varcoef(1600, 0, eps=0.9, name="bearing1600")
     if key.startswith("obstacle_ub_"):
         return instances.obstacle_ub(int(key.split("_")[-1]), 0)
     if key == "pressed512":

@@ -182,7 +182,7 @@ typedef struct {
 
 /* Fills the defaults: tol_rel 1e-8, tol_abs 0, eta1 0.1, eta2 0.05,
  * eta2_reduce 0.1, mu 0.01, max_outer 100000, max_gp 50, max_backtrack 60,
- * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 25,
+ * max_cg 0, FP64, mask free set, tile 0, chunk 0, use_graph 1, max_stall 100,
  * form GPCG_FORM_AUTO, tiles_per_wg 0, prefetch GPCG_PREFETCH_AUTO,
  * precond GPCG_PRECOND_NONE, cg_stop GPCG_CGSTOP_DECREASE,
  * cg_kernel GPCG_CGK_AUTO, lookahead GPCG_LOOKAHEAD_AUTO. */

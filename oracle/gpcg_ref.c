@@ -120,7 +120,7 @@ void ora_default_options(ora_options *o) {
   o->max_gp = 50;
   o->max_backtrack = 60;
   o->max_cg = 0;
-  o->max_stall = 25;
+  o->max_stall = 100;
   o->precond = 0;
   o->cg_stop = 0;
 }

@@ -661,7 +661,7 @@ void gpcg_options_default(gpcg_options *o) {
   o->tile = 0;
   o->chunk = 0;
   o->use_graph = 1;
-  o->max_stall = 25;
+  o->max_stall = 100;
   o->form = GPCG_FORM_AUTO;
   o->tiles_per_wg = 0;
   o->prefetch = GPCG_PREFETCH_AUTO;
