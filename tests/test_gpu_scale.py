@@ -106,3 +106,24 @@ def test_obstacle_metric_tolerance_error(N):
         if mism == 0:
             assert err2 <= 1.01 * pg / lmin + 1e-9
         res[prec] = x
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.9])
+def test_variable_coefficient_1600_converges(eps):
+    """The coefficient family of the paper's journal-bearing runs at their
+    size (1600^2, c = (1 + eps cos 2 pi s)^3, l = 0, u = inf), with the Jacobi
+    preconditioner: the solve ends with GPCG_OK (the projected-gradient norm
+    stays above its starting value for dozens of outer iterations while the
+    active set settles, which a stall safeguard must not take for the rounding
+    floor), the answer is feasible and the termination test holds when the
+    oracle's FP64 gradient re-evaluates it on the CPU."""
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.varcoef(1600, 0, eps=eps)
+    x, g, st = G.solve(inst, tol_rel=1e-8, precond=gpcg.GPCG_PRECOND_JACOBI)
+    print(f"varcoef1600 eps={eps}: status {st['status']}, outer {st['outer_iters']}, "
+          f"cg {st['cg_iters']}, pg {st['pg']:.3e}, tau {st['tau']:.3e}", flush=True)
+    assert st["status"] == gpcg.GPCG_OK, st
+    assert np.all(x >= inst.l) and np.all(x <= inst.u)
+    pg = cpu_pg(inst, x)
+    print(f"  pg recomputed on the CPU {pg:.3e}", flush=True)
+    assert pg <= st["tau"] * 1.001, (pg, st["tau"])
