@@ -1116,8 +1116,9 @@ __device__ void transition(const QPStatic *S, QPCore &d, const double *R, bool l
   }
 }
 
-// Runs the transition of the pending pass on a register copy of the core and
-// books the pass in the per-phase counters (thread 0, state in LDS).
+// Runs the transition of the pending pass on the LDS copy of the state and
+// books the pass in the per-phase counters (thread 0).  (A register copy of
+// the core was measured slower in the fused kernel: more VGPRs everywhere.)
 __device__ __forceinline__ void advance(const QPStatic *S, QPDyn &sd, const double *R,
                                        uint64_t now, bool la) {
   const int ph = sd.c.phase;
