@@ -466,10 +466,11 @@ def kernel_names(gpcg, args, tuned, ntiles, mixed, csr, precond):
     # form never runs in the CG-only kernel
     part = 1 if cgk and mat == "false" else 0
     pmat = "false" if part == 1 else mat
-    # the last template argument: one QP, no work queue
-    return (f"gpcg::pass_kernel<{flags}, {part}, {pmat}, false> (data kernel of the split "
+    # the last two template arguments: one QP (no work queue), generic
+    # gradient-projection passes
+    return (f"gpcg::pass_kernel<{flags}, {part}, {pmat}, false, false> (data kernel of the split "
             "form; the time per launch is that of one pass: transition and data kernels)",
-            f"pass_kernel<{flags}, {part}, {pmat}, false>")
+            f"pass_kernel<{flags}, {part}, {pmat}, false, false>")
 
 
 def run_single(gpcg, torch, dev, args, workload, steps, warmup, autotune=True):

@@ -193,6 +193,12 @@ constexpr int kVarMat = 8;
 // kVarQueue: the data kernels of the queue form (a fixed grid running the
 // items the transition kernel queued; never with kVarSpec).
 constexpr int kVarQueue = 16;
+// kVarLgp: the gradient-projection passes of stencil QPs take the lean path
+// (values shared through LDS; bitwise the generic path).  Set by batches and
+// the server; not with kVarSpec or kVarMat.  The kernel of one large QP keeps
+// the generic path: there the extra code slowed its CG passes by 2 %, and
+// gradient-projection passes are 1-2 % of its passes.
+constexpr int kVarLgp = 32;
 
 }  // namespace gpcg
 

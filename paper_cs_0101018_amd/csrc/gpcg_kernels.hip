@@ -1330,6 +1330,79 @@ __device__ __forceinline__ void cg_iter_prefetched(const CGView &V, const QPCore
   del = fmaT<CT>(z1, u1, del);
 }
 
+// GP_ALPHA or GP_TRIAL over one 256-unknown chunk of a stencil QP (thread t:
+// unknown k; own: k is an unknown of the tile).  The value each unknown
+// contributes to its neighbours' rows -- the projected gradient d_k (GP_ALPHA)
+// or the trial point and step (y_k, y_k - x_k) (GP_TRIAL) -- is evaluated
+// once by its owner and read by the west and east neighbours from LDS; the
+// values one grid row away, and beyond the chunk's first and last unknowns,
+// are evaluated from global memory.  Every value and every row is the
+// expression run_pass evaluates (apply_row / apply_row2), in the same order,
+// so the sums are bitwise those of the generic path.  Every thread calls it.
+__device__ __forceinline__ void gp_lean_chunk(const QPStatic *S, const QPCore &d, int phase,
+                                              int64_t k, bool own, double (&acc)[kNP]) {
+  __shared__ double s_va[kBlock], s_vb[kBlock];
+  const int t = (int)threadIdx.x;
+  const int c = d.cur;
+  const gptr<const double> x = gbl((const double *)S->x[c]);
+  const gptr<const double> g = gbl((const double *)S->g[c]);
+  const gptr<const double> l = gbl(S->l), u = gbl(S->u);
+  const bool trial = phase == PH_GP_TRIAL;
+  const double a = d.alpha;
+  const int32_t nx = S->nx;
+  const int32_t j = own ? (int32_t)(((uint64_t)k * S->div_magic) >> S->div_shift) : 0;
+  const int32_t i = own ? (int32_t)(k - (int64_t)j * nx) : 0;
+  const bool hasW = own && i > 0, hasE = own && i < nx - 1;
+  const bool hasS = own && j > 0, hasN = own && j < S->ny - 1;
+  auto val = [&](int64_t m) {
+    const double xm = x[m];
+    if (trial) {
+      const double ym = gp_point(xm, l[m], u[m], g[m], a);
+      return Pair{ym, ym - xm};
+    }
+    return Pair{proj_grad(xm, l[m], u[m], g[m]), 0.0};
+  };
+  const Pair z{0.0, 0.0};
+  const Pair cv = own ? val(k) : z;
+  s_va[t] = cv.y;
+  s_vb[t] = cv.s;
+  const Pair So = hasS ? val(k - nx) : z;
+  const Pair No = hasN ? val(k + nx) : z;
+  const Pair Wx = (t == 0 && hasW) ? val(k - 1) : z;
+  const Pair Ex = (t == kBlock - 1 && hasE) ? val(k + 1) : z;
+  __syncthreads();
+  const Pair W = !hasW ? z : (t > 0 ? Pair{s_va[t - 1], s_vb[t - 1]} : Wx);
+  const Pair E = !hasE ? z : (t < kBlock - 1 ? Pair{s_va[t + 1], s_vb[t + 1]} : Ex);
+  __syncthreads();  // the LDS rows are rewritten by the next chunk
+  if (!own) return;
+  Pair r;
+  if (S->op_kind == OPK_CONST) {
+    const double w = S->w;
+    r.y = w * ((cv.y - W.y) + (cv.y - E.y) + ((cv.y - So.y) + (cv.y - No.y)));
+    r.s = w * ((cv.s - W.s) + (cv.s - E.s) + ((cv.s - So.s) + (cv.s - No.s)));
+  } else {
+    const int64_t ex = (int64_t)j * (nx + 1) + i;
+    const int64_t ey = (int64_t)j * nx + i;
+    const gptr<const double> gx = gbl(S->wx), gy = gbl(S->wy);
+    const double wW = gx[ex], wE = gx[ex + 1], wS = gy[ey], wN = gy[ey + nx];
+    r.y = (wW * (cv.y - W.y) + wE * (cv.y - E.y)) + (wS * (cv.y - So.y) + wN * (cv.y - No.y));
+    r.s = (wW * (cv.s - W.s) + wE * (cv.s - E.s)) + (wS * (cv.s - So.s) + wN * (cv.s - No.s));
+  }
+  if (!trial) {  // GP_ALPHA: d'd and d'Ad for eq. (bqpls)
+    acc[0] = __fma_rn(cv.y, cv.y, acc[0]);
+    acc[1] = __fma_rn(cv.y, r.y, acc[1]);
+    return;
+  }
+  const double xk = x[k], lk = l[k], uk = u[k], gk = g[k], bk = gbl(S->b)[k];
+  const double gyk = r.y - bk;
+  gbl(S->x[c ^ 1])[k] = cv.y;
+  gbl(S->g[c ^ 1])[k] = gyk;
+  face_acc(cv.y, lk, uk, gyk, bk, acc);
+  acc[5] = __fma_rn(gk, cv.s, acc[5]);
+  acc[6] = __fma_rn(cv.s, r.s, acc[6]);
+  acc[7] += (is_active(cv.y, lk, uk) != is_active(xk, lk, uk)) ? 1.0 : 0.0;
+}
+
 // Operands of a gradient-projection pass at unknown k of a stencil QP, loaded
 // while the transition of the previous pass is still running: x, l, u, g at
 // k and its west, east, south and north neighbours (index 0..4; 0 outside the
@@ -1646,7 +1719,7 @@ constexpr int kPartAll = 0, kPartCG = 1, kPartRest = 2;
 // The pass of one work item (tiles [t0, t0 + nt) of QP q, clipped to its
 // tiles) with its state in LDS (sc, S) and its CG view V.  With SPEC the
 // operands of the first chunk are in P already (own: its unknown exists).
-template <typename CT, bool SPEC, bool PRE, int PART, bool MAT>
+template <typename CT, bool SPEC, bool PRE, int PART, bool MAT, bool LGP = false>
 __device__ __forceinline__ void pass_item(QPDev *q, int par, int t0, int nt, const QPCore &sc,
                                           const QPStatic *S, const CGView &V, int64_t kk,
                                           bool own, CGOperands<CT> &P) {
@@ -1700,6 +1773,24 @@ __device__ __forceinline__ void pass_item(QPDev *q, int par, int t0, int nt, con
     return;
   }
   if constexpr (PART == kPartCG) return;
+  if (LGP && (phase == PH_GP_ALPHA || phase == PH_GP_TRIAL) && S->op_kind != OPK_CSR) {
+    const int nchunk = S->tile / kBlock;
+    for (int tile = t0; tile < t1; ++tile) {
+      const int64_t k0 = (int64_t)tile * S->tile;
+      const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
+      double acc[kNP];
+      float accf[2] = {0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < kNP; ++k) acc[k] = 0.0;
+      for (int c = 0; c < nchunk; ++c) {
+        const int64_t k = k0 + (int64_t)c * kBlock + threadIdx.x;
+        gp_lean_chunk(S, sc, phase, k, k < k1, acc);
+      }
+      write_partial(slots, par ^ 1, phase, f32_slots(mixed, phase), tile, acc, accf);
+      if (tile + 1 < t1) __syncthreads();  // the reduction scratch is reused
+    }
+    return;
+  }
   for (int tile = t0; tile < t1; ++tile) {
     const int64_t k0 = (int64_t)tile * S->tile;
     const int64_t k1 = k0 + S->tile < S->n ? k0 + S->tile : S->n;
@@ -1714,7 +1805,7 @@ __device__ __forceinline__ void pass_item(QPDev *q, int par, int t0, int nt, con
 }
 
 template <typename CT, bool SPEC, bool PRE, int PART = kPartAll, bool MAT = false,
-          bool QUEUE = false>
+          bool QUEUE = false, bool LGP = false>
 __global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
   __shared__ QPCore sc;
   __shared__ QPStatic ss;
@@ -1739,7 +1830,7 @@ __global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
     if (tid < kCoreWords) reinterpret_cast<uint32_t *>(&sc)[tid] = core_w;
     if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
     __syncthreads();
-    pass_item<CT, false, PRE, PART, MAT>(q, par, it.tile0, it.ntile, sc, &ss, V, 0, false, P);
+    pass_item<CT, false, PRE, PART, MAT, LGP>(q, par, it.tile0, it.ntile, sc, &ss, V, 0, false, P);
   } else {
   QPDev *q;
   int t0, nt;
@@ -1768,7 +1859,7 @@ __global__ __launch_bounds__(kBlock, 4) void pass_kernel(StepLaunch L) {
   if (tid < kCoreWords) reinterpret_cast<uint32_t *>(&sc)[tid] = core_w;
   if (sw >= 0) reinterpret_cast<uint32_t *>(&ss)[sw] = st_w;
   __syncthreads();
-  pass_item<CT, SPEC, PRE, PART, MAT>(q, par, t0, nt, sc, &ss, V, kk, own, P);
+  pass_item<CT, SPEC, PRE, PART, MAT, LGP>(q, par, t0, nt, sc, &ss, V, kk, own, P);
   }
 }
 
@@ -2215,6 +2306,13 @@ template <int PART, bool QUEUE>
 static void *pass_ptr_q(int mixed, int variant) {
   const bool sp = !QUEUE && (variant & kVarSpec), pr = variant & kVarPre;
   if constexpr (PART != kPartCG) {
+    if ((variant & kVarLgp) && !sp && !(variant & kVarMat)) {
+      if (mixed)
+        return pr ? (void *)&pass_kernel<float, false, true, PART, false, QUEUE, true>
+                  : (void *)&pass_kernel<float, false, false, PART, false, QUEUE, true>;
+      return pr ? (void *)&pass_kernel<double, false, true, PART, false, QUEUE, true>
+                : (void *)&pass_kernel<double, false, false, PART, false, QUEUE, true>;
+    }
     if (variant & kVarMat) {
       if (mixed)
         return pr ? (void *)&pass_kernel<float, false, true, PART, true, QUEUE>
@@ -2251,7 +2349,7 @@ void *gpcg_pass_kernel_ptr(int mixed, int variant) {
 // The kernel of the passes the CG kernel skips: the early CG loads are of no
 // use there.
 void *gpcg_rest_kernel_ptr(int mixed, int variant) {
-  return pass_ptr<kPartRest>(mixed, variant & (kVarPre | kVarMat | kVarQueue));
+  return pass_ptr<kPartRest>(mixed, variant & (kVarPre | kVarMat | kVarQueue | kVarLgp));
 }
 
 int gpcg_launch_split(const StepLaunch &L, int mixed, int spec, void *stream) {

@@ -1284,7 +1284,7 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
       }
       COPY_OK(b->ws, b->stage_dev, b->tbytes, b->stream);
       COPY_OK(b->qcount, b->stage_dev + b->tbytes, 2 * sizeof(int32_t), b->stream);
-      const int spec = kVarQueue | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0) |
+      const int spec = kVarQueue | kVarLgp | (pre ? kVarPre : 0) | (b->cfg.cgk ? kVarCgk : 0) |
                        (mat ? kVarMat : 0);
       StepLaunch SL{};
       SL.qps = b->qptrs;
@@ -1338,7 +1338,8 @@ int gpcg_batch_solve(gpcg_batch b, const gpcg_problem *probs, int mode, gpcg_sta
         mat = mat || b->hs[i]->st.mrow != nullptr;
       }
       const int spec = (sp ? kVarSpec : 0) | (pre ? kVarPre : 0) |
-                       (split && b->cfg.cgk ? kVarCgk : 0) | (mat ? kVarMat : 0);
+                       (split && b->cfg.cgk ? kVarCgk : 0) | (mat ? kVarMat : 0) |
+                       (split ? kVarLgp : 0);
       hipGraphExec_t graph = nullptr;
       int rc = build_chain_graph(SL, b->mixed, spec, split ? 1 : 0, chunk, &graph);
       if (rc) return rc;
@@ -1948,7 +1949,7 @@ int gpcg_server_step(gpcg_server s, int *active) {
     const int mixed = s->opt.precision == GPCG_PREC_MIXED ? 1 : 0;
     for (int k = 0; k < s->opt.quantum; ++k) {
       SL.parity = k & 1;
-      if (gpcg_launch_split(SL, mixed, kVarQueue, s->stream) != 0)
+      if (gpcg_launch_split(SL, mixed, kVarQueue | kVarLgp, s->stream) != 0)
         return fail(GPCG_ERR_HIP, "pass kernel launch failed");
     }
     HIP_OK(hipEventRecord(s->chunk_ev[s->chunks & 1], s->stream));
