@@ -957,6 +957,16 @@ def main():
     import torch
     import paper_cs_0101018_amd as gpcg
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        # the calibration copy must be the largest copy of the run: no SpMV
+        # bandwidth figure (its reference copies reach 512 MiB)
+        args.no_spmv = True
+        a = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy-calib: 268435456 bytes read + written")
+        del a, b
     if args.workload in BATCH_WORKLOADS:
         args.batch_steps, args.batch_warmup = max(1, args.steps), args.warmup
         res, _ = bench_batch(args, gpcg, torch, dev, args.workload.endswith("mixed"))
@@ -968,16 +978,6 @@ def main():
         res, _ = bench_serve(args, gpcg, torch, dev, reqs)
         print(json.dumps(res), flush=True)
         return
-    if args.copy_calib:
-        # the calibration copy must be the largest copy of the run: no SpMV
-        # bandwidth figure (its reference copies reach 512 MiB)
-        args.no_spmv = True
-        a = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy-calib: 268435456 bytes read + written")
-        del a, b
     res, _, st, inst = run_single(gpcg, torch, dev, args, args.workload, args.steps, args.warmup)
     if args.extras:
         res["extras"] = spmv_extras(gpcg, torch, dev)
