@@ -111,9 +111,11 @@ typedef struct {
   int32_t tile;        /* unknowns per tile, the unit of one reduction slot
                           per pass (multiple of 256); 0 = library choice, a
                           function of n only: 256 up to 262,144 unknowns,
-                          512 beyond.  The tile fixes the summation order:
-                          the answer depends on it, and on nothing else of
-                          the launch set-up                                   */
+                          512 up to 8,388,607, 1024 up to 16,777,215, 2048
+                          from 16,777,216 (8192 tiles of 2048) on; the list
+                          and matrix free sets keep 256.  The tile fixes the
+                          summation order: the answer depends on it, and on
+                          nothing else of the launch set-up                   */
   int32_t chunk;       /* device passes per host check; 0 = library choice    */
   int32_t use_graph;   /* 1 = replay chunks as HIP graphs (default), 0 = launch */
   int32_t max_stall;   /* stop as GPCG_STAGNATED when ||P grad q|| after a

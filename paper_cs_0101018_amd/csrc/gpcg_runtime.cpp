@@ -132,11 +132,21 @@ constexpr int kFusedMaxTiles = 1024;
 // thread, up to 1024 x 256 unknowns; beyond that 512, which halves the slots
 // the transition of the split form sums.  Wider tiles save more slots but a
 // data workgroup sweeps the 256-unknown chunks of its tile one after the
-// other, and on the largest grids (1600^2 in FP64) 1024-unknown tiles lose
-// more there than they gain.  A function of n alone: a QP has the same tiles,
-// hence the same summation order and answer, alone, in a batch, in the server
-// and in every launch form.
-int tuned_tile(int64_t n) { return n > (int64_t)kFusedMaxTiles * kBlock ? 2 * kBlock : kBlock; }
+// other: at 1600^2 in FP64 (5000 tiles of 512) 1024-unknown tiles lose more
+// there than they gain (43.0 against 38.4 us per pass).  Once the grid holds
+// kWideTiles tiles even of 1024 or 2048 unknowns, the per-tile costs weigh
+// more: at 4096^2 in FP64, beyond the last-level cache, a pass takes 351 us
+// with 512-unknown tiles, 334 with 1024 and 321 with 2048 (the transition's
+// slot sum 21.6 -> 8.5 us, the data kernel 329 -> 312 us).  A function of n
+// alone: a QP has the same tiles, hence the same summation order and answer,
+// alone, in a batch, in the server and in every launch form.
+constexpr int64_t kWideTiles = 8192;
+int tuned_tile(int64_t n) {
+  if (n <= (int64_t)kFusedMaxTiles * kBlock) return kBlock;
+  for (int t : {8 * kBlock, 4 * kBlock})
+    if (n >= kWideTiles * t) return t;
+  return 2 * kBlock;
+}
 
 struct Layout {
   size_t qp, slots, pgpart, x1, g0, g1, rho0, rho1, uq0, uq1, sq0, sq1, p, w, mask;

@@ -64,6 +64,31 @@ def test_host_side_validation_without_gpu():
     assert gpcg.status_string(gpcg.GPCG_ERR_NOT_SPD).startswith("operator")
 
 
+def test_default_tile_rule():
+    """The library's tile is a function of n alone: 256 unknowns up to 1024
+    tiles of 256, then 512, then 1024 and 2048 once the grid holds 8192 tiles
+    of that width.  The workspace holds one slot block per tile, so the
+    default layout matches the explicit tile the rule names and no other."""
+    import paper_cs_0101018_amd as gpcg
+    nbytes = ctypes.c_size_t()
+
+    def ws(nx, ny, tile):
+        op = gpcg.gpcg_operator(kind=gpcg.GPCG_OP_STENCIL5_CONST, nx=nx, ny=ny, w=121.0)
+        opt = gpcg.default_options(tile=tile)
+        assert gpcg.gpcg_workspace_bytes(ctypes.byref(op), ctypes.byref(opt),
+                                         ctypes.byref(nbytes)) == gpcg.GPCG_OK
+        return nbytes.value
+
+    cases = [((512, 512), 256), ((512, 513), 512), ((1600, 1600), 512),
+             ((2048, 4095), 512), ((2048, 4096), 1024), ((4096, 4095), 1024),
+             ((4096, 4096), 2048), ((8192, 8192), 2048)]
+    for (nx, ny), tile in cases:
+        auto = ws(nx, ny, 0)
+        assert auto == ws(nx, ny, tile), (nx, ny, tile)
+        for other in {256, 512, 1024, 2048} - {tile}:
+            assert auto != ws(nx, ny, other), (nx, ny, other)
+
+
 def test_free_set_forms_host_checks():
     """The matrix free set needs a CSR operator and 256-unknown tiles; its
     workspace holds A_F (row offsets, column indices, values) on top of the

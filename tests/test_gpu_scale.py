@@ -1,6 +1,7 @@
 """Full-size obstacle problems with both bounds (1024^2 and 1600^2 unknowns; the
-1600^2 grid is the problem size of the paper's Table 1) on the GPU, through the
-same solver path the benchmark times.
+1600^2 grid is the problem size of the paper's Table 1; 4096^2, beyond the
+last-level cache, checked by properties only) on the GPU, through the same
+solver path the benchmark times.
 
 The reference x* is rebuilt on the CPU from a committed face certificate
 (``tests/golden/face_obstacle_ub_<N>_seed0.txt``, written by
@@ -106,6 +107,26 @@ def test_obstacle_metric_tolerance_error(N):
         if mism == 0:
             assert err2 <= 1.01 * pg / lmin + 1e-9
         res[prec] = x
+
+
+@pytest.mark.timeout(900)
+def test_obstacle_4096_default_tiles():
+    """The largest grid the benchmark times (4096^2, n = 16.8 M, five times the
+    last-level cache per pass) with the library's default tiles (2048 unknowns
+    at this size): the solve ends with GPCG_OK, the answer is feasible, and the
+    termination test holds when the oracle's FP64 gradient re-evaluates it on
+    the CPU (no x* at this size: an oracle solve would take hours)."""
+    import paper_cs_0101018_amd as gpcg
+    inst = instances.obstacle_ub(4096, 0)
+    print("4096^2: instance built", flush=True)
+    x, g, st = G.solve(inst, tol_rel=1e-8)
+    print(f"4096^2: status {st['status']}, outer {st['outer_iters']}, cg {st['cg_iters']}, "
+          f"passes {st['passes']}, pg {st['pg']:.3e}, tau {st['tau']:.3e}", flush=True)
+    assert st["status"] == gpcg.GPCG_OK, st
+    assert np.all(x >= inst.l) and np.all(x <= inst.u)
+    pg = cpu_pg(inst, x)
+    print(f"  pg recomputed on the CPU {pg:.3e}", flush=True)
+    assert pg <= st["tau"] * 1.001, (pg, st["tau"])
 
 
 @pytest.mark.parametrize("eps", [0.1, 0.9])

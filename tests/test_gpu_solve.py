@@ -185,19 +185,23 @@ def test_fused_and_split_forms_agree_bitwise(case):
         assert st["passes"] + st["lookaheads"] == s1["passes"] + s1["lookaheads"]
 
 
-def test_wider_tiles():
-    """512-unknown tiles (two unknowns per thread and pass, no early loads):
-    the same parity bar, and the launch forms agree bitwise."""
+@pytest.mark.parametrize("tile", [512, 1024, 2048])
+def test_wider_tiles(tile):
+    """Tiles of several 256-unknown chunks (no early loads; 512: two chunks
+    loaded together, 1024 and 2048: the library's tiles on the largest grids,
+    chunks in pairs or one after the other) on a ragged grid whose last tile
+    is partly empty: the same parity bar, and the launch forms agree bitwise."""
     import paper_cs_0101018_amd as gpcg
     inst = instances.obstacle(77, 3, amplitude=0.45, u_random=True)
     xs, gs, _ = reference("obst_ragged", inst)
-    x, g, st = G.solve(inst, tol_rel=TIGHT, tile=512)
+    x, g, st = G.solve(inst, tol_rel=TIGHT, tile=tile)
     assert st["status"] == gpcg.GPCG_OK, st
     assert G.rel_inf(x, xs) <= 1e-8
     check_faces(x, xs, gs, inst)
-    xf, _, _ = G.solve(inst, tile=512, form=gpcg.GPCG_FORM_FUSED)
-    xp, _, _ = G.solve(inst, tile=512, form=gpcg.GPCG_FORM_SPLIT)
-    assert np.array_equal(xf, xp)
+    xf, _, _ = G.solve(inst, tile=tile, form=gpcg.GPCG_FORM_FUSED)
+    xp, _, _ = G.solve(inst, tile=tile, form=gpcg.GPCG_FORM_SPLIT)
+    xq, _, _ = G.solve(inst, tile=tile, form=gpcg.GPCG_FORM_SPLIT, tiles_per_wg=2)
+    assert np.array_equal(xf, xp) and np.array_equal(xf, xq)
 
 
 def test_start_outside_box_is_projected():
