@@ -366,6 +366,9 @@ def cpu_headline_sample(key, max_outer, cg_iters):
                 gp=st["gp_iters"], cg_seconds=t_cg, cg_run=it)
 
 
+ONE_SOLVE_ALL_CORES = ("one solve: the oracle has no threaded code, so the host's other cores "
+                       "do not shorten it (OMP_NUM_THREADS=1 and =nproc run the same code)")
+
 def cpu_baseline_whole(inst, budget_s=12.0, precond=0, cg_stop=0):
     """The FP64 oracle, as it stands, on this host: solves/sec on a bounded
     sample (whole solves of the same workload until the budget is spent)."""
@@ -382,7 +385,8 @@ def cpu_baseline_whole(inst, budget_s=12.0, precond=0, cg_stop=0):
             break
     return dict(value=k / el, unit="solves/s", cores=1, kind="oracle",
                 sample=f"{k} complete solves of the same instance in {el:.1f} s "
-                       f"(single-threaded C, -O3 -ffp-contract=off)", **host_info())
+                       f"(single-threaded C, -O3 -ffp-contract=off)",
+                all_cores=dict(value=k / el, cores=1, how=ONE_SOLVE_ALL_CORES), **host_info())
 
 
 def cpu_baseline_projected(key, cg_full, max_outer=4, cg_iters=1000):
@@ -401,7 +405,9 @@ def cpu_baseline_projected(key, cg_full, max_outer=4, cg_iters=1000):
                        f"{max(cg_full - r['cg'], 0)} CG iterations of a whole solve (the GPU "
                        f"FP64 solve's count, {cg_full}, at the same tolerance) at that cost: "
                        f"{t_full:.0f} s per solve",
-                seconds_sampled=round(r["seconds"] + r["cg_seconds"], 2), **host_info())
+                seconds_sampled=round(r["seconds"] + r["cg_seconds"], 2),
+                all_cores=dict(value=1.0 / t_full, cores=1, how=ONE_SOLVE_ALL_CORES),
+                **host_info())
 
 
 def stratified(sizes, k):
@@ -881,16 +887,24 @@ def suite(args):
         # projected from the stratified sample
         tb = sum(r["seconds"] for r in bt) * 512 / len(bt)
         ts = sum(r["seconds"] for r in sv) * args.requests / len(sv)
+        # all cores: independent solves side by side, one per worker process;
+        # the one-thread times above were taken with every worker busy
+        many = (f"{workers} oracle solves at a time, one per worker process ({workers} of "
+                f"{info['cpus_available']} host CPUs; the GPU legs run meanwhile): {workers} x "
+                "the one-thread rate, which was measured with every worker busy")
         res["batch512"]["cpu_baseline"] = dict(
             value=round(512 / tb, 3), unit="solves/s", cores=1, kind="oracle",
             sample=f"{len(bt)} members stratified by size, timed one thread each "
                    f"({workers} worker processes at once); sum scaled to 512 members: "
-                   f"{tb:.0f} s", **info)
+                   f"{tb:.0f} s",
+            all_cores=dict(value=round(workers * 512 / tb, 3), cores=workers, how=many), **info)
         res["serve4096"]["cpu_baseline"] = dict(
             value=round(args.requests / ts, 3), unit="solves/s", cores=1, kind="oracle",
             sample=f"{len(sv)} requests stratified by size, timed one thread each "
                    f"({workers} worker processes at once); sum scaled to "
-                   f"{args.requests} requests: {ts:.0f} s", **info)
+                   f"{args.requests} requests: {ts:.0f} s",
+            all_cores=dict(value=round(workers * args.requests / ts, 3), cores=workers, how=many),
+            **info)
         # the headline's oracle time, alone on the host
         log("cpu leg: headline oracle sample")
         res["cpu_baseline"] = cpu_baseline_projected("obstacle_ub_1600", st64["cg_iters"])
