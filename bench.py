@@ -69,6 +69,8 @@ WORKLOADS = {
     # vectors per pass): every pass streams from HBM
     "obstacle4096_fp64": ("obstacle_ub_4096", dict(),
                           "GPCG FP64, obstacle 4096x4096 (n=16,777,216), both bounds, tol 1e-8 rel"),
+    "obstacle4096_mixed": ("obstacle_ub_4096", dict(precision=1),
+                           "GPCG mixed FP32-CG, obstacle 4096x4096 (n=16,777,216), both bounds"),
     "bearing256_fp64": ("bearing256", dict(), "GPCG FP64, -div(c grad u) 256x256, "
                         "c=(1+0.9 cos 2 pi s)^3 (eccentricity 0.9), l=0, u=inf, tol 1e-8 rel"),
     # the coefficient family of the paper's journal-bearing runs at their size

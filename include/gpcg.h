@@ -110,12 +110,13 @@ typedef struct {
   int32_t free_set;    /* GPCG_FREESET_*                                      */
   int32_t tile;        /* unknowns per tile, the unit of one reduction slot
                           per pass (multiple of 256); 0 = library choice, a
-                          function of n only: 256 up to 262,144 unknowns,
-                          512 up to 8,388,607, 1024 up to 16,777,215, 2048
-                          from 16,777,216 (8192 tiles of 2048) on; the list
-                          and matrix free sets keep 256.  The tile fixes the
-                          summation order: the answer depends on it, and on
-                          nothing else of the launch set-up                   */
+                          function of n and the precision only: 256 up to
+                          262,144 unknowns, 512 beyond, 1024 from 8,388,608
+                          (FP64) or 1,048,576 (mixed), 2048 from 16,777,216
+                          (8192 tiles of 2048) on; the list and matrix free
+                          sets keep 256.  The tile fixes the summation order:
+                          the answer depends on it, and on nothing else of
+                          the launch set-up                                   */
   int32_t chunk;       /* device passes per host check; 0 = library choice    */
   int32_t use_graph;   /* 1 = replay chunks as HIP graphs (default), 0 = launch */
   int32_t max_stall;   /* stop as GPCG_STAGNATED when ||P grad q|| after a

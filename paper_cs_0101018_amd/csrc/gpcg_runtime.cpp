@@ -137,14 +137,20 @@ constexpr int kFusedMaxTiles = 1024;
 // kWideTiles tiles even of 1024 or 2048 unknowns, the per-tile costs weigh
 // more: at 4096^2 in FP64, beyond the last-level cache, a pass takes 351 us
 // with 512-unknown tiles, 334 with 1024 and 321 with 2048 (the transition's
-// slot sum 21.6 -> 8.5 us, the data kernel 329 -> 312 us).  A function of n
-// alone: a QP has the same tiles, hence the same summation order and answer,
-// alone, in a batch, in the server and in every launch form.
+// slot sum 21.6 -> 8.5 us, the data kernel 329 -> 312 us).  The mixed form
+// moves half the CG bytes per unknown, so the per-tile costs weigh more
+// there: 1024-unknown tiles from 1024 such tiles on (1024^2: 15.15 -> 13.65
+// us per pass; 1600^2: 26.86 -> 26.13, where 2048 takes 29.58), 2048 from
+// the same size as in FP64 (4096^2: 197.6 us with 512, 174.1 with 1024,
+// 171.8 with 2048).  A function of n and the precision alone: a QP has the
+// same tiles, hence the same summation order and answer, alone, in a batch,
+// in the server and in every launch form.
 constexpr int64_t kWideTiles = 8192;
-int tuned_tile(int64_t n) {
+constexpr int64_t kWideTilesMixed = 1024;
+int tuned_tile(int64_t n, bool mixed) {
   if (n <= (int64_t)kFusedMaxTiles * kBlock) return kBlock;
-  for (int t : {8 * kBlock, 4 * kBlock})
-    if (n >= kWideTiles * t) return t;
+  if (n >= kWideTiles * 8 * kBlock) return 8 * kBlock;
+  if (n >= (mixed ? kWideTilesMixed : kWideTiles) * 4 * kBlock) return 4 * kBlock;
   return 2 * kBlock;
 }
 
@@ -164,7 +170,8 @@ Layout layout_for(const gpcg_operator *op, int precision, int tile_opt, int free
   const size_t ct = mixed ? 4 : 8;
   // the list and matrix forms compact the free set tile by tile with one
   // unknown per thread: they keep 256-unknown tiles at every size
-  L.tile = tile_opt > 0 ? tile_opt : (free_set != GPCG_FREESET_MASK ? kBlock : tuned_tile(n));
+  L.tile = tile_opt > 0 ? tile_opt
+                        : (free_set != GPCG_FREESET_MASK ? kBlock : tuned_tile(n, mixed));
   L.ntiles = (int)((n + L.tile - 1) / L.tile);
   size_t off = 0;
   auto take = [&](size_t bytes) {

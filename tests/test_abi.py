@@ -64,24 +64,28 @@ def test_host_side_validation_without_gpu():
     assert gpcg.status_string(gpcg.GPCG_ERR_NOT_SPD).startswith("operator")
 
 
-def test_default_tile_rule():
-    """The library's tile is a function of n alone: 256 unknowns up to 1024
-    tiles of 256, then 512, then 1024 and 2048 once the grid holds 8192 tiles
-    of that width.  The workspace holds one slot block per tile, so the
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_default_tile_rule(mixed):
+    """The library's tile is a function of n and the precision alone: 256
+    unknowns up to 1024 tiles of 256, then 512, then 1024 once the grid holds
+    8192 tiles of 1024 (mixed: 1024 of them), and 2048 once it holds 8192
+    tiles of 2048.  The workspace holds one slot block per tile, so the
     default layout matches the explicit tile the rule names and no other."""
     import paper_cs_0101018_amd as gpcg
     nbytes = ctypes.c_size_t()
+    prec = gpcg.GPCG_PREC_MIXED if mixed else gpcg.GPCG_PREC_FP64
 
     def ws(nx, ny, tile):
         op = gpcg.gpcg_operator(kind=gpcg.GPCG_OP_STENCIL5_CONST, nx=nx, ny=ny, w=121.0)
-        opt = gpcg.default_options(tile=tile)
+        opt = gpcg.default_options(tile=tile, precision=prec)
         assert gpcg.gpcg_workspace_bytes(ctypes.byref(op), ctypes.byref(opt),
                                          ctypes.byref(nbytes)) == gpcg.GPCG_OK
         return nbytes.value
 
-    cases = [((512, 512), 256), ((512, 513), 512), ((1600, 1600), 512),
-             ((2048, 4095), 512), ((2048, 4096), 1024), ((4096, 4095), 1024),
-             ((4096, 4096), 2048), ((8192, 8192), 2048)]
+    cases = [((512, 512), 256), ((512, 513), 512), ((1024, 1023), 512),
+             ((1024, 1024), 1024 if mixed else 512), ((1600, 1600), 1024 if mixed else 512),
+             ((2048, 4095), 1024 if mixed else 512), ((2048, 4096), 1024),
+             ((4096, 4095), 1024), ((4096, 4096), 2048), ((8192, 8192), 2048)]
     for (nx, ny), tile in cases:
         auto = ws(nx, ny, 0)
         assert auto == ws(nx, ny, tile), (nx, ny, tile)

@@ -185,22 +185,27 @@ def test_fused_and_split_forms_agree_bitwise(case):
         assert st["passes"] + st["lookaheads"] == s1["passes"] + s1["lookaheads"]
 
 
-@pytest.mark.parametrize("tile", [512, 1024, 2048])
-def test_wider_tiles(tile):
+@pytest.mark.parametrize("tile,mixed", [(512, False), (1024, False), (2048, False),
+                                        (1024, True), (2048, True)],
+                         ids=["512", "1024", "2048", "1024_mixed", "2048_mixed"])
+def test_wider_tiles(tile, mixed):
     """Tiles of several 256-unknown chunks (no early loads; 512: two chunks
     loaded together, 1024 and 2048: the library's tiles on the largest grids,
-    chunks in pairs or one after the other) on a ragged grid whose last tile
-    is partly empty: the same parity bar, and the launch forms agree bitwise."""
+    the mixed form's from 1024^2 on, chunks one after the other) on a ragged
+    grid whose last tile is partly empty: the parity bar of the precision
+    (FP64 1e-8, mixed 1e-6 against x*), and the launch forms agree bitwise."""
     import paper_cs_0101018_amd as gpcg
     inst = instances.obstacle(77, 3, amplitude=0.45, u_random=True)
     xs, gs, _ = reference("obst_ragged", inst)
-    x, g, st = G.solve(inst, tol_rel=TIGHT, tile=tile)
+    prec = gpcg.GPCG_PREC_MIXED if mixed else gpcg.GPCG_PREC_FP64
+    x, g, st = G.solve(inst, tol_rel=1e-10 if mixed else TIGHT, tile=tile, precision=prec)
     assert st["status"] == gpcg.GPCG_OK, st
-    assert G.rel_inf(x, xs) <= 1e-8
+    assert G.rel_inf(x, xs) <= (1e-6 if mixed else 1e-8)
     check_faces(x, xs, gs, inst)
-    xf, _, _ = G.solve(inst, tile=tile, form=gpcg.GPCG_FORM_FUSED)
-    xp, _, _ = G.solve(inst, tile=tile, form=gpcg.GPCG_FORM_SPLIT)
-    xq, _, _ = G.solve(inst, tile=tile, form=gpcg.GPCG_FORM_SPLIT, tiles_per_wg=2)
+    xf, _, _ = G.solve(inst, tile=tile, precision=prec, form=gpcg.GPCG_FORM_FUSED)
+    xp, _, _ = G.solve(inst, tile=tile, precision=prec, form=gpcg.GPCG_FORM_SPLIT)
+    xq, _, _ = G.solve(inst, tile=tile, precision=prec, form=gpcg.GPCG_FORM_SPLIT,
+                       tiles_per_wg=2)
     assert np.array_equal(xf, xp) and np.array_equal(xf, xq)
 
 
