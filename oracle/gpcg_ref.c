@@ -52,7 +52,7 @@
  *    with eq. (cgstop1), ||r_k + A_k w_j|| <= eta_2 ||r_k||, measured in the
  *    M^{-1} norm when preconditioned; the default is eq. (cgstop1).
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
+ * Build: gcc -O3 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
  * round-to-nearest, sequential sums in index order).
  */
 #include <math.h>
