@@ -59,3 +59,14 @@ def test_workload_table():
         inst = bench.make_instance(key)
         assert inst.n > 0 and desc
     assert bench.make_instance("obstacle_ub_1024").N == 1024
+
+
+def test_cpu_baseline_reports_one_thread_and_all_cores():
+    """The oracle baseline states the threads it used, the host, and an
+    all-cores figure (the oracle has no threaded code: for one solve both
+    figures are the same)."""
+    import instances
+    r = bench.cpu_baseline_whole(instances.obstacle50(0), budget_s=0.2)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
+    assert r["all_cores"]["value"] == r["value"] and r["all_cores"]["cores"] == 1
+    assert "cpu_model" in r and r["cpus_available"] >= 1
